@@ -1,0 +1,478 @@
+"""Pins of the CPU oracle against what mathematics fixes (no GPU).
+
+Each test pins one part of the method to a closed form, an invariant, a special
+case that reduces to a textbook result, or an exact/self-similar solution, so
+that a plausible slip (dropped term, wrong sign or index, swapped operand) in
+the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2401_03378_amd import workloads as W
+import analytic as A
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ULP = np.finfo(np.float64).eps
+
+
+class P2:   # a bare problem description for the point-wise entry points
+    def __init__(self, ndim=3, gamma=1.4):
+        self.ndim, self.recon, self.rk = ndim, 0, 2
+        self.gamma, self.cfl, self.dx, self.dy, self.dz = gamma, 0.8, 1.0, 1.0, 1.0
+        self.blocks = np.zeros(0, dtype=W.BLOCK_DTYPE)
+        self.links = np.zeros(0, dtype=W.LINK_DTYPE)
+        self.ncell = 0
+
+
+def _rand_prims(rng, n, ndim=3):
+    Wp = np.zeros((n, 5))
+    Wp[:, 0] = np.exp(0.5 * rng.standard_normal(n))
+    Wp[:, 1:1 + ndim] = rng.standard_normal((n, ndim))
+    Wp[:, 4] = np.exp(0.5 * rng.standard_normal(n))
+    return Wp
+
+
+# ----------------------------------------------------------------- EOS (T1)
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_eos_roundtrip_and_closed_form(ndim):
+    rng = np.random.default_rng(1)
+    prob = P2(ndim)
+    Wp = _rand_prims(rng, 2000, ndim)
+    U, F, c = O.state_flux(prob, Wp, 0)
+    Wb, bad = O.eos(prob, U)
+    assert bad == 0
+    cols = [0] + list(range(1, 1 + ndim)) + [4]
+    rel = np.abs(Wb[:, cols] - Wp[:, cols]) / np.abs(Wp[:, cols])
+    assert rel.max() < 64 * ULP
+    # closed form p = (gamma-1)(E - |m|^2/(2 rho)) in long double
+    Ul = U.astype(np.longdouble)
+    m2 = sum(Ul[:, 1 + d] ** 2 for d in range(ndim))
+    p = (np.longdouble(1.4) - 1) * (Ul[:, -1] - m2 / (2 * Ul[:, 0]))
+    assert np.max(np.abs((Wb[:, 4] - p) / p)) < 64 * ULP
+    # sound speed closed form
+    assert np.allclose(c, np.sqrt(1.4 * Wp[:, 4] / Wp[:, 0]), rtol=8 * ULP, atol=0)
+
+
+def test_eos_flags_nonphysical():
+    prob = P2(3)
+    U = np.array([[1.0, 0, 0, 0, 1.0], [-1.0, 0, 0, 0, 1.0], [1.0, 2.0, 0, 0, 1.0],
+                  [np.nan, 0, 0, 0, 1.0]])
+    _, bad = O.eos(prob, U)
+    assert bad == 3
+
+
+# -------------------------------------------------------------- PLM-MC (T2)
+
+def test_plm_linear_exact_and_extremum():
+    q = np.array([[1.0, 2.0, 3.0], [5.0, 3.0, 1.0], [0.0, 0.0, 0.0],
+                  [1.0, 3.0, 2.0], [2.0, 1.0, 2.0], [1.0, 1.0, 5.0]])
+    qm, qp, code = O.plm(q)
+    assert list(qm[:2]) == [1.5, 4.0] and list(qp[:2]) == [2.5, 2.0]
+    assert list(code[:2]) == [1, 1]
+    # extrema and flat one side: slope zero
+    assert list(qm[2:]) == [0.0, 3.0, 1.0, 1.0] and list(qp[2:]) == [0.0, 3.0, 1.0, 1.0]
+    assert list(code[2:]) == [0, 0, 0, 0]
+
+
+def test_plm_limiter_branches():
+    # backward diff 1, forward 10: central 5.5 > 2*1 -> slope 2
+    qm, qp, code = O.plm(np.array([[0.0, 1.0, 11.0], [0.0, 10.0, 11.0], [0.0, 1.0, 2.5]]))
+    assert code[0] == 2 and qp[0] == 2.0 and qm[0] == 0.0
+    assert code[1] == 3 and qp[1] == 11.0 and qm[1] == 9.0
+    assert code[2] == 1 and qp[2] == 1.625 and qm[2] == 0.375
+
+
+def test_plm_tvd_and_sign_symmetry():
+    rng = np.random.default_rng(2)
+    q = rng.standard_normal((5000, 3))
+    qm, qp, _ = O.plm(q)
+    lo = np.minimum(q[:, 0], q[:, 2])
+    hi = np.maximum(q[:, 0], q[:, 2])
+    lo = np.minimum(lo, q[:, 1])
+    hi = np.maximum(hi, q[:, 1])
+    # faces stay within the values of the neighbouring cells (MC is TVD)
+    assert np.all(qp <= np.maximum(q[:, 1], q[:, 2]) + 1e-15)
+    assert np.all(qp >= np.minimum(q[:, 1], q[:, 2]) - 1e-15)
+    assert np.all(qm <= np.maximum(q[:, 0], q[:, 1]) + 1e-15)
+    assert np.all(qm >= np.minimum(q[:, 0], q[:, 1]) - 1e-15)
+    qm2, qp2, _ = O.plm(-q)
+    assert np.array_equal(qm2, -qm) and np.array_equal(qp2, -qp)
+    qm3, qp3, _ = O.plm(q[:, ::-1].copy())     # mirror: faces swap
+    assert np.array_equal(qm3, qp) and np.array_equal(qp3, qm)
+
+
+# --------------------------------------------------------------- WENO5 (T3)
+
+def test_weno5_quadratic_exact():
+    """Cell averages of any quadratic give its exact face values whatever the
+    nonlinear weights (each candidate is exact for quadratics)."""
+    rng = np.random.default_rng(3)
+    n = 200
+    a, b, c = rng.standard_normal((3, n))
+    # cell i at [i-1/2, i+1/2]; average of a + b x + c x^2 is a + b i + c (i^2 + 1/12)
+    i = np.arange(-2, 3)[None, :]
+    q = a[:, None] + b[:, None] * i + c[:, None] * (i * i + 1.0 / 12.0)
+    qm, qp = O.weno5(q)
+    f = lambda x: a + b * x + c * x * x
+    scale = np.abs(a) + np.abs(b) + np.abs(c)
+    assert np.max(np.abs(qp - f(0.5)) / scale) < 1e-14
+    assert np.max(np.abs(qm - f(-0.5)) / scale) < 1e-14
+
+
+def test_weno5_order_and_linear_weights():
+    errs = []
+    for N in (20, 40, 80, 160):
+        h = 1.0 / N
+        x = (np.arange(N) + 0.5) * h
+        # exact cell averages of sin(2 pi x) + 0.2 (smooth, no critical point at faces)
+        avg = lambda xc: (np.cos(2 * np.pi * (xc - h / 2)) - np.cos(2 * np.pi * (xc + h / 2))) / (2 * np.pi * h) + 0.2
+        st = np.stack([avg(x + k * h) for k in range(-2, 3)], axis=1)
+        qm, qp = O.weno5(st)
+        err = np.max(np.abs(qp - (np.sin(2 * np.pi * (x + h / 2)) + 0.2)))
+        errs.append(err)
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    assert orders[-1] > 4.5, orders
+    # on smooth data the weights tend to (0.1, 0.6, 0.3): the result tends to
+    # the fifth-order linear upwind interpolant (2a - 13b + 47c + 27d - 3e)/60
+    N = 400
+    h = 1.0 / N
+    x = (np.arange(N) + 0.5) * h
+    st = np.stack([np.sin(2 * np.pi * (x + k * h)) + 3.0 for k in range(-2, 3)], axis=1)
+    qm, qp = O.weno5(st)
+    lin = (2 * st[:, 0] - 13 * st[:, 1] + 47 * st[:, 2] + 27 * st[:, 3] - 3 * st[:, 4]) / 60
+    assert np.max(np.abs(qp - lin)) < 1e-9
+
+
+def test_weno5_step_is_essentially_non_oscillatory():
+    q = np.array([[1.0, 1.0, 1.0, 0.0, 0.0], [1.0, 1.0, 0.0, 0.0, 0.0]])
+    qm, qp = O.weno5(q)
+    assert np.all(qp > -1e-6) and np.all(qp < 1 + 1e-6)
+    assert abs(qp[0] - 1.0) < 1e-4 and abs(qp[1]) < 1e-4   # upwind side chosen
+
+
+# ---------------------------------------------------------------- HLLC (T4)
+
+def _euler_flux(Wp, n, g, ndim):
+    rho, p = Wp[:, 0], Wp[:, 4]
+    u = Wp[:, 1:1 + ndim]
+    E = p / (g - 1) + 0.5 * rho * np.sum(u * u, axis=1)
+    F = np.zeros((Wp.shape[0], ndim + 2))
+    F[:, 0] = rho * u[:, n]
+    for d in range(ndim):
+        F[:, 1 + d] = rho * u[:, n] * u[:, d]
+    F[:, 1 + n] += p
+    F[:, -1] = (E + p) * u[:, n]
+    return F
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_hllc_consistency(ndim):
+    rng = np.random.default_rng(4)
+    prob = P2(ndim)
+    Wp = _rand_prims(rng, 1000, ndim)
+    for n in range(ndim):
+        F, tape, bad = O.hllc(prob, Wp, Wp, n)
+        ref = _euler_flux(Wp, n, 1.4, ndim)
+        assert bad == 0
+        assert np.max(np.abs(F - ref) / (np.abs(ref) + 1.0)) < 1e-14
+
+
+def test_hllc_supersonic_upwind_bitwise():
+    rng = np.random.default_rng(5)
+    prob = P2(3)
+    WL = _rand_prims(rng, 100)
+    WR = _rand_prims(rng, 100)
+    WL[:, 1] = 10.0 + np.abs(WL[:, 1])
+    WR[:, 1] = 10.0 + np.abs(WR[:, 1])
+    F, tape, _ = O.hllc(prob, WL, WR, 0)
+    _, FL, _ = O.state_flux(prob, WL, 0)
+    assert np.all(tape & 3 == 0) and np.array_equal(F, FL)
+    WL[:, 1] *= -1
+    WR[:, 1] *= -1
+    F, tape, _ = O.hllc(prob, WL, WR, 0)
+    _, FR, _ = O.state_flux(prob, WR, 0)
+    assert np.all(tape & 3 == 3) and np.array_equal(F, FR)
+
+
+def test_hllc_contacts_exact():
+    """HLLC resolves isolated contacts exactly: a stationary contact carries no
+    mass or energy flux and momentum flux p; a moving one is upwinded."""
+    prob = P2(3)
+    WL = np.array([[1.0, 0.0, 0.3, -0.2, 0.7]])
+    WR = np.array([[0.25, 0.0, -0.1, 0.4, 0.7]])
+    F, tape, _ = O.hllc(prob, WL, WR, 0)
+    assert F[0, 0] == 0.0 and F[0, 4] == 0.0 and F[0, 1] == 0.7
+    WL[0, 1] = WR[0, 1] = 0.3
+    F, tape, _ = O.hllc(prob, WL, WR, 0)
+    ref = _euler_flux(WL, 0, 1.4, 3)
+    assert np.allclose(F, ref, rtol=1e-14, atol=1e-15)
+    WL[0, 1] = WR[0, 1] = -0.3
+    F, tape, _ = O.hllc(prob, WL, WR, 0)
+    ref = _euler_flux(WR, 0, 1.4, 3)
+    assert np.allclose(F, ref, rtol=1e-14, atol=1e-15)
+
+
+def test_hllc_mirror_symmetry():
+    rng = np.random.default_rng(6)
+    prob = P2(3)
+    WL = _rand_prims(rng, 500)
+    WR = _rand_prims(rng, 500)
+    F, _, _ = O.hllc(prob, WL, WR, 1)
+    mL, mR = WR.copy(), WL.copy()
+    mL[:, 2] *= -1
+    mR[:, 2] *= -1
+    G, _, _ = O.hllc(prob, mL, mR, 1)
+    sgn = np.array([-1, 1, -1, 1, -1.0])   # odd in the normal direction
+    sgn = np.array([-1.0, -1.0, 1.0, -1.0, -1.0])
+    assert np.allclose(G, sgn * F, rtol=1e-13, atol=1e-13)
+
+
+def _hllc_flux_form(WL, WR, n, g, ndim):
+    """HLLC through Toro's flux form F*_K = [S*(S_K U_K - F_K) + S_K p*_K D*]
+    / (S_K - S*) with p*_K = p_K + rho_K (S_K - u_K)(S* - u_K) and
+    D* = (0, e_n, S*) -- algebraically equal to the star-state form, written
+    along a different route (Toro 2009, Sec. 10.4.2)."""
+    out = np.zeros((WL.shape[0], ndim + 2))
+    for i in range(WL.shape[0]):
+        def prep(Wk):
+            rho, u, p = Wk[0], Wk[1:1 + ndim], Wk[4]
+            E = p / (g - 1) + 0.5 * rho * np.dot(u, u)
+            U = np.concatenate([[rho], rho * u, [E]])
+            F = np.concatenate([[rho * u[n]], rho * u[n] * u, [(E + p) * u[n]]])
+            F[1 + n] += p
+            return rho, u, p, U, F, math.sqrt(g * p / rho)
+        rL, uL, pL, UL, FL, cL = prep(WL[i])
+        rR, uR, pR, UR, FR, cR = prep(WR[i])
+        SL = min(uL[n] - cL, uR[n] - cR)
+        SR = max(uL[n] + cL, uR[n] + cR)
+        Ss = (pR - pL + rL * uL[n] * (SL - uL[n]) - rR * uR[n] * (SR - uR[n])) / (
+            rL * (SL - uL[n]) - rR * (SR - uR[n]))
+        D = np.zeros(ndim + 2)
+        D[1 + n] = 1.0
+        D[-1] = Ss
+        if SL >= 0:
+            out[i] = FL
+        elif SR <= 0:
+            out[i] = FR
+        else:
+            r, u, p, U, F, S = (rL, uL, pL, UL, FL, SL) if Ss >= 0 else (rR, uR, pR, UR, FR, SR)
+            ps = p + r * (S - u[n]) * (Ss - u[n])
+            out[i] = (Ss * (S * U - F) + S * ps * D) / (S - Ss)
+    return out
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_hllc_equals_flux_form(ndim):
+    rng = np.random.default_rng(9)
+    prob = P2(ndim)
+    WL = _rand_prims(rng, 3000, ndim)
+    WR = _rand_prims(rng, 3000, ndim)
+    for n in range(ndim):
+        F, tape, _ = O.hllc(prob, WL, WR, n)
+        ref = _hllc_flux_form(WL, WR, n, 1.4, ndim)
+        assert set(np.unique(tape & 3)) == {0, 1, 2, 3}
+        assert np.max(np.abs(F - ref) / (np.abs(ref).max(axis=1, keepdims=True) + 1e-300)) < 1e-11
+
+
+def test_exact_riemann_solver_against_table():
+    gold = json.load(open(os.path.join(GOLD, "sod_exact_star.json")))
+    _, _, _, info = A.riemann_sample(*gold["left"], *gold["right"], gold["gamma"], [0.0])
+    for k in ("p_star", "u_star", "rho_starL", "rho_starR", "right_shock", "rare_head", "rare_tail"):
+        assert round(info[k], 5) == pytest.approx(gold[k], abs=1e-5), k
+
+
+# ----------------------------------------------------------- CFL dt (T12)
+
+def test_cfl_dt_closed_form():
+    p = W.random_blocks(3, 4, 2, seed=0, gamma=1.5)
+    U = p.U0
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    # rho = 0.5, p = 3 -> c = sqrt(1.5*3/0.5) = 3; u = (1, -2, 0.5)
+    rho, u, pr = 0.5, (1.0, -2.0, 0.5), 3.0
+    U[0, m] = rho
+    for d in range(3):
+        U[1 + d, m] = rho * u[d]
+    U[4, m] = pr / 0.5 + 0.5 * rho * sum(x * x for x in u)
+    p.dx = p.dy = p.dz = 1.0 / 64
+    dt = O.cfl_dt(p, U)
+    assert dt == 0.8 / (4.0 * 64 + 5.0 * 64 + 3.5 * 64)
+
+
+# ------------------------------------------------------ invariants (T5-T10)
+
+@pytest.mark.parametrize("ndim,recon,rk", [(2, 0, 2), (3, 0, 2), (2, 1, 3), (3, 1, 3)])
+def test_free_stream(ndim, recon, rk):
+    p = W.random_blocks(ndim, 8 if ndim == 2 else 6, 3 if recon else 2, seed=0,
+                        recon=recon, rk=rk)
+    m = W.interior_mask(p.blocks, p.ncell, ndim)
+    vals = [1.3, 0.4, -0.7, 0.2, 2.9][:ndim + 1] + [2.9]
+    for v in range(ndim + 2):
+        p.U0[v, m] = vals[v]
+    U = p.U0.copy()
+    for _ in range(3):
+        O.step(p, U)
+    if rk == 2:
+        assert np.array_equal(U[:, m], p.U0[:, m])
+    else:   # Shu-Osher combinations with 3/4, 1/3 round: a few ulp per stage
+        assert np.max(np.abs(U[:, m] - p.U0[:, m]) / np.abs(p.U0[:, m])) < 16 * ULP
+
+
+@pytest.mark.parametrize("ndim,recon,rk", [(2, 0, 2), (3, 0, 2), (2, 1, 3), (3, 1, 3)])
+def test_periodic_conservation(ndim, recon, rk):
+    p = W.random_blocks(ndim, 8 if ndim == 2 else 6, 3 if recon else 2, seed=7,
+                        recon=recon, rk=rk)
+    m = W.interior_mask(p.blocks, p.ncell, ndim)
+    U = p.U0.copy()
+    tot0 = [math.fsum(U[v, m]) for v in range(ndim + 2)]
+    scale = [math.fsum(np.abs(U[v, m])) for v in range(ndim + 2)]
+    for s in range(4):
+        O.step(p, U)
+        for v in range(ndim + 2):
+            assert abs(math.fsum(U[v, m]) - tot0[v]) <= 1e-13 * (s + 1) * scale[v]
+
+
+def test_sod_rows_identical_and_transpose():
+    px = W.sod2d(N=32, n=16, nsteps=10)
+    py = W.sod2d(N=32, n=16, nsteps=10, axis=1)
+    Ux, Uy = px.U0.copy(), py.U0.copy()
+    dx = O.run(px, Ux, 10)
+    dy = O.run(py, Uy, 10)
+    assert dx == dy
+    Gx = W.gather_global(Ux, px.blocks, px.grid, 2)[:, 0]
+    Gy = W.gather_global(Uy, py.blocks, py.grid, 2)[:, 0]
+    assert np.all(Gx == Gx[:, :1, :])               # every row identical
+    assert np.all(Gx[2] == 0.0)                      # no transverse momentum
+    assert np.array_equal(Gx[0], Gy[0].T) and np.array_equal(Gx[3], Gy[3].T)
+    assert np.array_equal(Gx[1], Gy[2].T) and np.array_equal(Gx[2], Gy[1].T)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_block_decomposition_invariance(ndim):
+    N = 32 if ndim == 2 else 16
+    gens = []
+    for n in ((8, 16, 32) if ndim == 2 else (4, 8, 16)):
+        if ndim == 2:
+            p = W.sod2d(N=N, n=n)
+            # a 2D random field instead of Sod so that every direction matters
+            r = W.random_blocks(2, n, 2, seed=11, NB=(N // n, N // n, 1))
+        else:
+            r = W.random_blocks(3, n, 3, seed=11, recon=1, rk=3, NB=(N // n,) * 3)
+        gens.append(r)
+    # same global field in every decomposition (the generator draws globally)
+    G0 = W.gather_global(gens[0].U0, gens[0].blocks, gens[0].grid, ndim)
+    outs = []
+    for r in gens:
+        U = r.U0.copy()
+        W.scatter_global(U, G0, r.blocks, r.grid, ndim)
+        O.run(r, U, 2)
+        outs.append(W.gather_global(U, r.blocks, r.grid, ndim))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_nan_padding_untouched_by_stencils():
+    """Every input carries NaN in all padding; a read of an edge or corner, or
+    of a guard before it is filled, would show up as NaN in the interior."""
+    for r in (W.random_blocks(3, 6, 3, seed=1, recon=1, rk=3, bc="outflow"),
+              W.random_blocks(2, 8, 2, seed=1)):
+        U = r.U0.copy()
+        O.run(r, U, 2)
+        m = W.interior_mask(r.blocks, r.ncell, r.ndim)
+        assert np.all(np.isfinite(U[:, m]))
+
+
+# ------------------------------------------------------ exact solutions
+
+def _line_problem(N, recon, rk, ng, fields, dx, bc_x="periodic"):
+    """A single block of N x 1 (2D) cells; y periodic-self."""
+    blocks, ncell = W.make_table([(N, ng, 1)], ng, 2)
+    links = np.zeros(1, dtype=W.LINK_DTYPE)
+    links["nbr"] = [W.PERIODIC_SELF if bc_x == "periodic" else W.OUTFLOW] * 2 + [W.PERIODIC_SELF] * 2 + [0, 0]
+    U = W.empty_state(4, ncell)
+    rho, u, p = fields
+    G = W.conserved(rho, [u, np.zeros_like(u)], p, 1.4)
+    view = W.interior(U, blocks, 0, 2)
+    view[...] = np.broadcast_to(G[:, None, None, :], view.shape)
+    return W.Problem("line", 2, recon, rk, 1.4, 0.8, dx, dx, 1.0, blocks, links, ncell, 0, U)
+
+
+def _run_to(p, U, t_end):
+    t = 0.0
+    while t < t_end - 1e-15:
+        dt = O.cfl_dt(p, U)
+        dt = min(dt, t_end - t)
+        O.step(p, U, dt)
+        t += dt
+
+
+def test_sod_exact_solution_convergence():
+    errs = []
+    for N in (64, 128, 256):
+        x = (np.arange(N) + 0.5) / N
+        rho = np.where(x < 0.5, 1.0, 0.125)
+        pr = np.where(x < 0.5, 1.0, 0.1)
+        p = _line_problem(N, 0, 2, 2, (rho, 0 * x, pr), 1.0 / N, bc_x="outflow")
+        U = p.U0.copy()
+        _run_to(p, U, 0.2)
+        r_num = W.interior(U, p.blocks, 0, 2)[0, 0, 0]
+        r_ex, _, _, _ = A.riemann_sample(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1.4, (x - 0.5) / 0.2)
+        errs.append(np.mean(np.abs(r_num - r_ex)))
+    assert errs[0] < 1e-2
+    assert errs[0] > errs[1] > errs[2]
+    assert math.log2(errs[0] / errs[2]) / 2 > 0.6
+
+
+@pytest.mark.parametrize("recon,rk,order", [(0, 2, 1.8), (1, 3, 2.9)])
+def test_entropy_wave_order(recon, rk, order):
+    errs = []
+    for N in (32, 64, 128):
+        h = 1.0 / N
+        x = (np.arange(N) + 0.5) * h
+        avg = lambda s: 1.0 + 0.2 * (np.cos(2 * np.pi * (s - h / 2)) - np.cos(2 * np.pi * (s + h / 2))) / (2 * np.pi * h)
+        ng = 3 if recon else 2
+        p = _line_problem(N, recon, rk, ng, (avg(x), np.ones(N), np.ones(N)), h)
+        U = p.U0.copy()
+        _run_to(p, U, 0.25)
+        r_num = W.interior(U, p.blocks, 0, 2)[0, 0, 0]
+        errs.append(np.mean(np.abs(r_num - avg(x - 0.25))))
+    obs = math.log2(errs[1] / errs[2])
+    assert obs > order, (errs, obs)
+
+
+def test_sedov_symmetry_and_radius():
+    gold = json.load(open(os.path.join(GOLD, "sedov_constant.json")))
+    p = W.sedov3d(N=32, n=16, radius_cells=3.5)
+    U = p.U0.copy()
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    E0 = math.fsum(U[4, m])
+    t = 0.0
+    steps = 0
+    while t < 0.04:
+        dt = O.step(p, U)
+        t += dt
+        steps += 1
+    G = W.gather_global(U, p.blocks, p.grid, 3)
+    rho = G[0]
+    s = np.max(np.abs(rho))
+    # octant mirror symmetry and axis permutation (rounding-order differences only)
+    assert np.max(np.abs(rho - rho[::-1, :, :])) <= 1e-12 * s
+    assert np.max(np.abs(rho - rho[:, ::-1, :])) <= 1e-12 * s
+    assert np.max(np.abs(rho - rho.transpose(1, 0, 2))) <= 1e-12 * s
+    assert np.max(np.abs(rho - rho.transpose(2, 1, 0))) <= 1e-12 * s
+    assert np.max(np.abs(G[1] + G[1][:, :, ::-1])) <= 1e-12 * np.max(np.abs(G[1]))
+    # energy conserved while the blast stays inside the domain
+    assert abs(math.fsum(U[4, m]) - E0) <= 1e-12 * E0
+    # shock radius from the density maximum along the axes vs the similarity law
+    N = 32
+    xc = (np.arange(N) + 0.5) / N - 0.5
+    rr = np.sqrt(xc[:, None, None] ** 2 + xc[None, :, None] ** 2 + xc[None, None, :] ** 2)
+    shell = rho > 1.0 + 0.5 * (rho.max() - 1.0)
+    R_num = np.sum(rr * rho * shell) / np.sum(rho * shell)
+    R_ex = A.sedov_radius(1.0, t, 1.0, gold["xi0"])
+    assert abs(R_num - R_ex) / R_ex < 0.1, (R_num, R_ex, steps)
+    assert 2.0 < rho.max() < 6.0       # compression below the strong-shock limit
