@@ -1,0 +1,159 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) FP64 block-structured
+ * compressible-Euler step.
+ *
+ * What it computes.  One explicit time step of the unsplit finite-volume
+ * method for the Euler equations of an ideal gas, on a table of blocks each
+ * surrounded by guard cells (the paper's block-structured mesh, Sec. 2.2
+ * "Flash-X").  The step is the non-telescoping SSP-RK loop of the paper's
+ * Sec. 4.2 (the "traditional" listing: per stage, fill guard cells, then for
+ * every block do the intra-stage calculations), with the intra-stage chain of
+ * the paper's Algorithm "Intra stage calculations for Spark": reconstruction
+ * (calcLims), Riemann fluxes (calcFlux), solution update (updSoln) and EOS
+ * (calcEos).  The paper names these steps only; the formulas are the textbook
+ * methods they stand for: ideal-gas EOS; MC-limited piecewise-linear
+ * (van Leer 1977) or WENO5-JS (Jiang & Shu 1996) reconstruction of primitive
+ * variables; HLLC fluxes with Davis wave speeds (Toro 2009, Sec. 10.4);
+ * Shu-Osher SSP-RK2/RK3 (Gottlieb & Shu 1998); CFL time step from the
+ * unsplit wave-speed sum.
+ *
+ * Data layout (all state arrays).  One float64 array of nvar x ncell_total,
+ * variable-major (v * ncell_total + cell), nvar = ndim + 2, variables
+ * (rho, m_x, m_y[, m_z], E).  Block b owns the padded cells
+ * [offset, offset + (nx+2ng)(ny+2ng)(nz+2ng)) of every variable plane, x
+ * fastest; in 2D nz = 1 and there is no z padding.  Only interior cells are
+ * results; guard, edge and corner cells of the caller's arrays are never
+ * read by the step kernels (guards are gathered from their source cells).
+ *
+ * Ownership.  Arrays passed to the ctx functions are DEVICE pointers on the
+ * ctx's device, owned by the caller, and must stay valid until the work
+ * enqueued on the ctx's stream completes.  Descriptor tables passed to
+ * hydro_create / hydro_validate are HOST pointers, copied.  The ctx owns its
+ * device tables, stage buffers, partial-reduction buffers and graphs.  A ctx
+ * is bound to one stream and is not thread-safe.
+ *
+ * Errors.  Every int-returning function returns HYDRO_OK or a negative code;
+ * hydro_last_error(ctx) gives text.  Kernel-detected non-physical states
+ * (rho <= 0, p <= 0, NaN) are counted on the device and reported by
+ * hydro_status (HYDRO_ENONPHYS); no floors are applied.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYDRO_OK 0
+#define HYDRO_EINVAL (-1)     /* bad argument, descriptor table or dt <= 0  */
+#define HYDRO_EHIP (-2)       /* HIP runtime error (text in hydro_last_error) */
+#define HYDRO_ENONPHYS (-3)   /* non-physical state met by a kernel         */
+#define HYDRO_ENOMEM (-4)     /* device allocation failed                   */
+
+#define HYDRO_PLM_MC 0
+#define HYDRO_WENO5 1
+
+#define HYDRO_OUTFLOW (-1)        /* zero-gradient copy of the nearest interior cell */
+#define HYDRO_PERIODIC_SELF (-2)  /* periodic wrap onto the block itself */
+
+/* One block: interior extents, guard width, first padded cell (per plane). */
+typedef struct {
+    int32_t nx, ny, nz, ng;
+    int64_t offset;
+} hydro_block_t;
+
+/* Face links in order (-x, +x, -y, +y, -z, +z): >= 0 neighbour block index,
+ * HYDRO_OUTFLOW or HYDRO_PERIODIC_SELF.  Neighbours must match in the
+ * transverse extents and in ng, and be at least ng cells deep. */
+typedef struct {
+    int32_t nbr[6];
+} hydro_link_t;
+
+typedef struct {
+    int32_t ndim;     /* 2 or 3 */
+    int32_t recon;    /* HYDRO_PLM_MC (needs ng >= 2) or HYDRO_WENO5 (ng >= 3) */
+    int32_t rk;       /* 2 or 3 SSP-RK stages */
+    int32_t flags;    /* reserved, 0 */
+    double gamma;     /* ratio of specific heats, > 1 */
+    double cfl;       /* Courant number of the unsplit sum, > 0 */
+    double dx, dy, dz;  /* cell widths (dz ignored in 2D but must be > 0) */
+} hydro_params_t;
+
+/* Launch configuration of the stage kernels (chosen by an autotuner). */
+#define HYDRO_MODE_PERSISTENT 0  /* one launch per stage over all blocks */
+#define HYDRO_MODE_PERBLOCK 1    /* per block: guard-fill launch + stage launch */
+typedef struct {
+    int32_t mode;       /* HYDRO_MODE_* */
+    int32_t tile;       /* xy tile of a work item: 0 = 8x8, 1 = 16x8, 2 = 16x16 */
+    int32_t grid;       /* workgroups of a persistent launch; 0 = one per work item */
+    int32_t zchunk;     /* z planes per work item; 0 = the whole block */
+    int32_t use_graph;  /* replay hydro_step from a captured hipGraph */
+    int32_t xcd;        /* place a block's work items on one XCD (L2) */
+} hydro_tuning_t;
+
+typedef struct hydro_ctx hydro_ctx_t;
+
+/* Host-only check of a problem description (no GPU use).  Returns HYDRO_OK
+ * or HYDRO_EINVAL: null pointer, ndim/recon/rk out of range, gamma <= 1,
+ * cfl or dx <= 0, extents < 1, ng below the stencil's need, 2D block with
+ * nz != 1, offsets out of range or overlapping, link index out of range,
+ * neighbour faces that do not match. */
+int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks,
+                   const hydro_link_t *links, int32_t nblocks, int64_t ncell_total);
+
+/* Create a context on the current HIP device for the given problem; work is
+ * enqueued on `stream` (a hipStream_t; NULL = default stream).  Validates as
+ * hydro_validate, uploads the tables, allocates stage buffers and picks a
+ * default tuning.  *out receives the context (NULL on error). */
+int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks,
+                 const hydro_link_t *links, int32_t nblocks, int64_t ncell_total,
+                 void *stream, hydro_ctx_t **out);
+
+/* Replace / read the launch configuration.  Invalidates captured graphs. */
+int hydro_set_tuning(hydro_ctx_t *ctx, const hydro_tuning_t *tuning);
+int hydro_get_tuning(hydro_ctx_t *ctx, hydro_tuning_t *tuning);
+
+/* Fill the ng face guard layers of every block of U in place (neighbour
+ * interior, periodic wrap or outflow copy; edges and corners untouched). */
+int hydro_fill_guards(hydro_ctx_t *ctx, double *U);
+
+/* CFL time step dt = cfl / max over interior cells of
+ * sum_d (|u_d| + c) / dx_d, computed from U; written to dt_dev (one device
+ * double).  Asynchronous. */
+int hydro_cfl_dt(hydro_ctx_t *ctx, const double *U, double *dt_dev);
+
+/* One SSP-RK stage s (1-based):  T = Us + dt L(Us);  Uout = T for s = 1,
+ * else Uout = b_s T + a_s Un with (a,b) = (1/2,1/2) [RK2], (3/4,1/4) and
+ * (1/3,2/3) [RK3].  Reads the interiors of Un and Us (guards are gathered
+ * from their sources), writes the interior of Uout.  Uout may alias Un, not
+ * Us.  dt is read from dt_dev on the device. */
+int hydro_rk_stage(hydro_ctx_t *ctx, int32_t stage, const double *dt_dev,
+                   const double *Un, const double *Us, double *Uout);
+
+/* One full step in place on U.  If compute_dt != 0 the CFL dt of U is first
+ * written to dt_dev; otherwise the value already in dt_dev is used. */
+int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
+
+/* Vector-Jacobian product of one step with dt held fixed (the branch
+ * decisions of limiters, fallback and Riemann solver are those of the forward
+ * step at Un): gUn = (dU^{n+1}/dU^n)^T gUnext over interior cells; the
+ * padding of gUn is set to 0.  gUn must not alias gUnext. */
+int hydro_step_vjp(hydro_ctx_t *ctx, const double *Un, const double *dt_dev,
+                   const double *gUnext, double *gUn);
+
+/* Wait for the ctx's stream; *n_nonphys (may be NULL) receives the number of
+ * non-physical events counted since the last call, then the count is reset.
+ * Returns HYDRO_ENONPHYS if that number is non-zero. */
+int hydro_status(hydro_ctx_t *ctx, int64_t *n_nonphys);
+
+/* Text of the last error on this ctx (valid until the next call on it). */
+const char *hydro_last_error(hydro_ctx_t *ctx);
+
+void hydro_destroy(hydro_ctx_t *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYDRO_H */

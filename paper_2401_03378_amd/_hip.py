@@ -1,0 +1,108 @@
+"""ctypes binding of libhydro.so (the C ABI in include/hydro.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  There is no fallback; if the library is missing, loading fails
+with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libhydro.so")
+
+HYDRO_OK, HYDRO_EINVAL, HYDRO_EHIP, HYDRO_ENONPHYS, HYDRO_ENOMEM = 0, -1, -2, -3, -4
+MODE_PERSISTENT, MODE_PERBLOCK = 0, 1
+TILES = {0: (8, 8), 1: (16, 8), 2: (16, 16)}
+
+EXPORTS = ("hydro_validate", "hydro_create", "hydro_set_tuning", "hydro_get_tuning",
+           "hydro_fill_guards", "hydro_cfl_dt", "hydro_rk_stage", "hydro_step",
+           "hydro_step_vjp", "hydro_status", "hydro_last_error", "hydro_destroy")
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hydro error {code}: {msg}")
+        self.code = code
+
+
+class Block(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("ng", C.c_int32), ("offset", C.c_int64)]
+
+
+class Link(C.Structure):
+    _fields_ = [("nbr", C.c_int32 * 6)]
+
+
+class Params(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("recon", C.c_int32), ("rk", C.c_int32),
+                ("flags", C.c_int32), ("gamma", C.c_double), ("cfl", C.c_double),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
+                ("zchunk", C.c_int32), ("use_graph", C.c_int32), ("xcd", C.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"{LIB} is not built; run `python -m paper_2401_03378_amd.build` "
+                               "(or __graft_entry__.build())")
+        L = C.CDLL(LIB)
+        vp, dp, i32, i64 = C.c_void_p, C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "hydro_validate": (C.c_int, [C.POINTER(Params), C.POINTER(Block), C.POINTER(Link), i32, i64]),
+            "hydro_create": (C.c_int, [C.POINTER(Params), C.POINTER(Block), C.POINTER(Link), i32, i64, vp,
+                                       C.POINTER(vp)]),
+            "hydro_set_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+            "hydro_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+            "hydro_fill_guards": (C.c_int, [vp, dp]),
+            "hydro_cfl_dt": (C.c_int, [vp, dp, dp]),
+            "hydro_rk_stage": (C.c_int, [vp, i32, dp, dp, dp, dp]),
+            "hydro_step": (C.c_int, [vp, dp, dp, i32]),
+            "hydro_step_vjp": (C.c_int, [vp, dp, dp, dp, dp]),
+            "hydro_status": (C.c_int, [vp, C.POINTER(C.c_int64)]),
+            "hydro_last_error": (C.c_char_p, [vp]),
+            "hydro_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def tables(prob):
+    """ctypes params/blocks/links of a problem description (duck-typed)."""
+    blocks = np.ascontiguousarray(prob.blocks)
+    links = np.ascontiguousarray(prob.links)
+    nb = len(blocks)
+    B = (Block * max(nb, 1))()
+    L = (Link * max(nb, 1))()
+    for i in range(nb):
+        b = blocks[i]
+        B[i] = Block(int(b["nx"]), int(b["ny"]), int(b["nz"]), int(b["ng"]), int(b["offset"]))
+        for f in range(6):
+            L[i].nbr[f] = int(links[i]["nbr"][f])
+    P = Params(int(prob.ndim), int(prob.recon), int(prob.rk), 0, float(prob.gamma),
+               float(prob.cfl), float(prob.dx), float(prob.dy), float(prob.dz))
+    return P, B, L, nb
+
+
+def validate(prob) -> int:
+    P, B, L, nb = tables(prob)
+    return lib().hydro_validate(C.byref(P), B, L, nb, int(prob.ncell))

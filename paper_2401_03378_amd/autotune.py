@@ -1,0 +1,99 @@
+"""Autotuner for the stage launch configuration.
+
+Searches tile shape (8x8, 16x8, 16x16 columns per work item), z-chunking of
+work items, the persistent grid size and the XCD placement of a block's work
+items.  Every candidate must reproduce the reference candidate's state bit
+for bit after two steps (the kernels are deterministic and the launch shape
+must not change a single rounding), then the fastest by timed steps wins.
+Results are cached in a JSON file keyed by device and problem signature.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuning_cache.json")
+
+
+def signature(prob) -> str:
+    b = np.ascontiguousarray(prob.blocks)
+    h = hashlib.sha256(b.tobytes() + np.ascontiguousarray(prob.links).tobytes()).hexdigest()[:12]
+    try:
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        arch = "unknown"
+    return f"{arch}|d{prob.ndim}|r{prob.recon}|rk{prob.rk}|nb{len(b)}|{h}"
+
+
+def candidates(prob, ncu):
+    out = []
+    zch = [0] if prob.ndim == 2 else [0, 8]
+    for tile in (0, 1, 2):
+        for zc in zch:
+            for grid in (0, 2 * ncu, 4 * ncu):
+                for xcd in (0, 1):
+                    if xcd and grid == 0:
+                        continue
+                    out.append(dict(mode=0, tile=tile, zchunk=zc, grid=grid, xcd=xcd, use_graph=1))
+    return out
+
+
+def _time_steps(S, U, nsteps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        S.step(U)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / nsteps
+
+
+def search(S, prob, nsteps=5, log=print):
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    U0 = S.to_device(prob.U0)
+    ref = None
+    best = None
+    results = []
+    for cand in candidates(prob, ncu):
+        S.set_tuning(**cand)
+        U = U0.clone()
+        S.step(U)
+        S.step(U)
+        S.status()
+        if ref is None:
+            ref = U.clone()
+        elif not torch.equal(torch.nan_to_num(U, nan=0.0), torch.nan_to_num(ref, nan=0.0)):
+            raise RuntimeError(f"tuning candidate {cand} changed the result")
+        t = _time_steps(S, U, nsteps)
+        results.append((t, cand))
+        log(f"autotune {cand}: {t * 1e3:.3f} ms/step")
+        if best is None or t < best[0]:
+            best = (t, cand)
+    S.set_tuning(**best[1])
+    return best[1], results
+
+
+def tuned_or_search(S, prob, log=print, cache=CACHE):
+    sig = signature(prob)
+    db = {}
+    if os.path.exists(cache):
+        try:
+            db = json.load(open(cache))
+        except ValueError:
+            db = {}
+    if sig in db:
+        S.set_tuning(**db[sig]["tuning"])
+        return db[sig]["tuning"]
+    best, results = search(S, prob, log=log)
+    db[sig] = {"tuning": best, "ms_per_step": min(t for t, _ in results) * 1e3}
+    try:
+        with open(cache, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+    except OSError:
+        pass
+    return best

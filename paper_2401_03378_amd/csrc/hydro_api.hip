@@ -1,0 +1,564 @@
+// C ABI of the FP64 Euler step (declared in include/hydro.h): validation,
+// device tables, the work-item list, stage buffers, the SSP-RK step driver
+// and its hipGraph replay.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hydro.h"
+#include "hydro_kernels.h"
+
+using namespace hydro;
+
+struct hydro_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;       // caller's stream
+    hipStream_t cap = nullptr;          // private stream used only for graph capture
+    hydro_params_t prm{};
+    int32_t nblocks = 0;
+    int64_t ncell = 0;
+    int nv = 0;
+    std::vector<hydro_block_t> hb;
+    std::vector<hydro_link_t> hl;
+    DevBlock *d_blocks = nullptr;
+    FaceSrc *d_faces = nullptr;
+    std::vector<DevBlock> h_dev;
+    std::vector<FaceSrc> h_faces;
+    // work list (persistent order) and per-block order with ranges
+    WorkItem *d_items = nullptr;
+    int nitems = 0;
+    WorkItem *d_items_pb = nullptr;
+    std::vector<int> pb_start;
+    double *d_buf[2] = {nullptr, nullptr};
+    double *d_partial = nullptr;
+    int partial_cap = 0;
+    unsigned long long *d_nbad = nullptr;
+    hydro_tuning_t tune{};
+    std::string err;
+    // captured step
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const double *g_U = nullptr;
+    const double *g_dt = nullptr;
+    int g_cdt = -1;
+    // adjoint scratch
+    double *d_vjp = nullptr;
+    size_t vjp_bytes = 0;
+};
+
+namespace {
+
+int fail(hydro_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(hydro_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, HYDRO_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                  \
+    do {                                                  \
+        hipError_t _e = (expr);                           \
+        if (_e != hipSuccess) return hip_fail((c), _e, #expr); \
+    } while (0)
+
+int extent(const hydro_block_t &b, int d) { return d == 0 ? b.nx : (d == 1 ? b.ny : b.nz); }
+
+int64_t padded_cells(const hydro_block_t &b, int ndim)
+{
+    int64_t pz = (ndim == 3) ? b.nz + 2 * b.ng : 1;
+    return (int64_t)(b.nx + 2 * b.ng) * (b.ny + 2 * b.ng) * pz;
+}
+
+std::string check_problem(const hydro_params_t *p, const hydro_block_t *blocks, const hydro_link_t *links,
+                          int32_t nblocks, int64_t ncell)
+{
+    if (!p) return "null params";
+    if (nblocks < 0 || ncell < 0) return "negative sizes";
+    if (nblocks > 0 && (!blocks || !links)) return "null descriptor table";
+    if (p->ndim != 2 && p->ndim != 3) return "ndim must be 2 or 3";
+    if (p->recon != HYDRO_PLM_MC && p->recon != HYDRO_WENO5) return "unknown reconstruction";
+    if (p->rk != 2 && p->rk != 3) return "rk must be 2 or 3";
+    if (!(p->gamma > 1.0)) return "gamma must be > 1";
+    if (!(p->cfl > 0.0) || !(p->dx > 0.0) || !(p->dy > 0.0) || !(p->dz > 0.0)) return "cfl and cell widths must be > 0";
+    const int ngmin = (p->recon == HYDRO_WENO5) ? 3 : 2;
+    std::vector<std::pair<int64_t, int64_t>> span(nblocks);
+    for (int b = 0; b < nblocks; ++b) {
+        const hydro_block_t &B = blocks[b];
+        if (B.nx < 1 || B.ny < 1 || B.nz < 1) return "block " + std::to_string(b) + ": extent < 1";
+        if (B.nx > 32767 || B.ny > 32767 || B.nz > 32767) return "block " + std::to_string(b) + ": extent too large";
+        if (B.ng < ngmin) return "block " + std::to_string(b) + ": ng below the stencil's need";
+        if (p->ndim == 2 && B.nz != 1) return "block " + std::to_string(b) + ": 2D block with nz != 1";
+        const int64_t sz = padded_cells(B, p->ndim);
+        if (B.offset < 0 || B.offset + sz > ncell) return "block " + std::to_string(b) + ": offset out of range";
+        span[b] = {B.offset, B.offset + sz};
+    }
+    std::sort(span.begin(), span.end());
+    for (int b = 1; b < nblocks; ++b)
+        if (span[b].first < span[b - 1].second) return "blocks overlap";
+    for (int b = 0; b < nblocks; ++b) {
+        const hydro_block_t &B = blocks[b];
+        for (int d = 0; d < p->ndim; ++d)
+            for (int side = 0; side < 2; ++side) {
+                const int nb = links[b].nbr[2 * d + side];
+                if (nb >= nblocks || nb < -2) return "block " + std::to_string(b) + ": link out of range";
+                if (nb == HYDRO_OUTFLOW) continue;
+                const hydro_block_t &S = (nb >= 0) ? blocks[nb] : B;
+                for (int e = 0; e < p->ndim; ++e)
+                    if (e != d && extent(S, e) != extent(B, e))
+                        return "block " + std::to_string(b) + ": neighbour face size mismatch";
+                if (extent(S, d) < B.ng) return "block " + std::to_string(b) + ": neighbour shallower than ng";
+                if (S.ng != B.ng) return "block " + std::to_string(b) + ": neighbour ng differs";
+            }
+    }
+    return "";
+}
+
+// Host tables: geometry and, per face, the source of its guard layers.
+void build_tables(hydro_ctx *c)
+{
+    const int nd = c->prm.ndim;
+    c->h_dev.resize(c->nblocks);
+    c->h_faces.assign((size_t)c->nblocks * 6, FaceSrc{0, 0, 0, 0, 0});
+    for (int b = 0; b < c->nblocks; ++b) {
+        const hydro_block_t &B = c->hb[b];
+        DevBlock D{};
+        D.off = B.offset;
+        D.nx = B.nx; D.ny = B.ny; D.nz = B.nz; D.ng = B.ng;
+        D.px = B.nx + 2 * B.ng;
+        D.py = B.ny + 2 * B.ng;
+        D.gz = (nd == 3) ? B.ng : 0;
+        c->h_dev[b] = D;
+    }
+    for (int b = 0; b < c->nblocks; ++b) {
+        const hydro_block_t &B = c->hb[b];
+        for (int d = 0; d < nd; ++d)
+            for (int side = 0; side < 2; ++side) {
+                const int nb = c->hl[b].nbr[2 * d + side];
+                const int n = extent(B, d);
+                FaceSrc f{};
+                const hydro_block_t &S = (nb >= 0) ? c->hb[nb] : B;
+                f.off = S.offset;
+                f.px = S.nx + 2 * S.ng;
+                f.py = S.ny + 2 * S.ng;
+                if (nb == HYDRO_OUTFLOW) {           // nearest interior cell
+                    f.A = (side == 0) ? 0 : n - 1;
+                    f.B = 0;
+                } else {                             // neighbour or periodic: distance l-1 from the face
+                    const int m = extent(S, d);
+                    f.A = (side == 0) ? m : -n;
+                    f.B = 1;
+                }
+                c->h_faces[(size_t)b * 6 + 2 * d + side] = f;
+            }
+    }
+}
+
+int tile_x(int t) { return t == 0 ? 8 : 16; }
+int tile_y(int t) { return t == 2 ? 16 : 8; }
+
+// Work items: xy tiles of every block over z chunks.  The persistent list is
+// sorted by decreasing size (largest first); with xcd != 0 the items of one
+// block are placed at list positions congruent modulo 8, so a fixed-stride
+// persistent grid (a multiple of 8 workgroups) keeps them on one XCD.
+void build_items(hydro_ctx *c, std::vector<WorkItem> &list, std::vector<WorkItem> &perblock, std::vector<int> &start)
+{
+    const int TX = tile_x(c->tune.tile), TY = tile_y(c->tune.tile);
+    const int nd = c->prm.ndim;
+    perblock.clear();
+    start.assign(c->nblocks + 1, 0);
+    for (int b = 0; b < c->nblocks; ++b) {
+        const hydro_block_t &B = c->hb[b];
+        const int nz = (nd == 3) ? B.nz : 1;
+        const int zc = (nd == 3 && c->tune.zchunk > 0) ? c->tune.zchunk : nz;
+        start[b] = (int)perblock.size();
+        for (int z0 = 0; z0 < nz; z0 += zc)
+            for (int y0 = 0; y0 < B.ny; y0 += TY)
+                for (int x0 = 0; x0 < B.nx; x0 += TX) {
+                    WorkItem w{};
+                    w.block = b;
+                    w.xy = x0 | (y0 << 16);
+                    const int nzi = std::min(zc, nz - z0);
+                    w.z = z0 | (nzi << 16);
+                    w.cost = std::min(TX, B.nx - x0) * std::min(TY, B.ny - y0) * nzi;
+                    perblock.push_back(w);
+                }
+    }
+    start[c->nblocks] = (int)perblock.size();
+    list = perblock;
+    std::stable_sort(list.begin(), list.end(), [](const WorkItem &a, const WorkItem &b) { return a.cost > b.cost; });
+    if (c->tune.xcd) {
+        // deal blocks round-robin onto 8 lanes, keep each lane's items in
+        // order, then interleave the lanes position by position
+        std::vector<std::vector<WorkItem>> lane(8);
+        std::vector<int> lane_of(c->nblocks, -1);
+        int next = 0;
+        for (const WorkItem &w : list) {
+            if (lane_of[w.block] < 0) lane_of[w.block] = (next++) % 8;
+            lane[lane_of[w.block]].push_back(w);
+        }
+        std::vector<WorkItem> out;
+        out.reserve(list.size());
+        size_t maxl = 0;
+        for (auto &l : lane) maxl = std::max(maxl, l.size());
+        for (size_t r = 0; r < maxl; ++r)
+            for (int q = 0; q < 8; ++q)
+                if (r < lane[q].size()) out.push_back(lane[q][r]);
+        list.swap(out);
+    }
+}
+
+int upload_items(hydro_ctx *c)
+{
+    std::vector<WorkItem> list, pb;
+    build_items(c, list, pb, c->pb_start);
+    if (c->d_items) (void)hipFree(c->d_items);
+    if (c->d_items_pb) (void)hipFree(c->d_items_pb);
+    c->d_items = c->d_items_pb = nullptr;
+    c->nitems = (int)list.size();
+    const size_t bytes = sizeof(WorkItem) * std::max<size_t>(1, list.size());
+    HIP_TRY(c, hipMalloc(&c->d_items, bytes));
+    HIP_TRY(c, hipMalloc(&c->d_items_pb, bytes));
+    if (!list.empty()) {
+        HIP_TRY(c, hipMemcpy(c->d_items, list.data(), sizeof(WorkItem) * list.size(), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_items_pb, pb.data(), sizeof(WorkItem) * pb.size(), hipMemcpyHostToDevice));
+    }
+    const int need = std::max(1, c->nitems);
+    if (need > c->partial_cap) {
+        if (c->d_partial) (void)hipFree(c->d_partial);
+        c->d_partial = nullptr;
+        HIP_TRY(c, hipMalloc(&c->d_partial, sizeof(double) * need));
+        c->partial_cap = need;
+    }
+    return HYDRO_OK;
+}
+
+void drop_graph(hydro_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_U = c->g_dt = nullptr;
+    c->g_cdt = -1;
+}
+
+void rk_coeffs(int rk, int s, double &a, double &b)
+{
+    a = 0.0;
+    b = 1.0;
+    if (rk == 2 && s == 2) { a = 0.5; b = 0.5; }
+    if (rk == 3 && s == 2) { a = 0.75; b = 0.25; }
+    if (rk == 3 && s == 3) { a = 1.0 / 3.0; b = 2.0 / 3.0; }
+}
+
+StageArgs stage_args(hydro_ctx *c, int s, const double *dt, const double *Un, const double *Us, double *Uout)
+{
+    StageArgs a{};
+    a.blocks = c->d_blocks;
+    a.faces = c->d_faces;
+    a.items = c->d_items;
+    a.nitems = c->nitems;
+    a.stage = s;
+    a.nc = c->ncell;
+    a.gamma = c->prm.gamma;
+    a.g1 = c->prm.gamma - 1.0;
+    a.ig1 = 1.0 / (c->prm.gamma - 1.0);
+    a.idx = 1.0 / c->prm.dx;
+    a.idy = 1.0 / c->prm.dy;
+    a.idz = 1.0 / c->prm.dz;
+    rk_coeffs(c->prm.rk, s, a.a, a.b);
+    a.dt = dt;
+    a.Un = Un;
+    a.Us = Us;
+    a.Uout = Uout;
+    a.nbad = c->d_nbad;
+    return a;
+}
+
+int persistent_grid(hydro_ctx *c)
+{
+    int g = c->tune.grid > 0 ? std::min(c->tune.grid, c->nitems) : c->nitems;
+    return g;
+}
+
+int enqueue_cfl(hydro_ctx *c, const double *U, double *dt, hipStream_t st)
+{
+    CflArgs a{};
+    a.blocks = c->d_blocks;
+    a.items = c->d_items;
+    a.nitems = c->nitems;
+    a.nc = c->ncell;
+    a.gamma = c->prm.gamma;
+    a.g1 = c->prm.gamma - 1.0;
+    a.idx = 1.0 / c->prm.dx;
+    a.idy = 1.0 / c->prm.dy;
+    a.idz = 1.0 / c->prm.dz;
+    a.U = U;
+    a.partial = c->d_partial;
+    a.nbad = c->d_nbad;
+    const int grid = std::max(1, std::min(persistent_grid(c), c->partial_cap));
+    hipError_t e = launch_cfl(a, c->prm.ndim, c->tune.tile, grid, c->prm.cfl, dt, st);
+    if (e != hipSuccess) return hip_fail(c, e, "cfl launch");
+    return HYDRO_OK;
+}
+
+int enqueue_guards(hydro_ctx *c, double *U, int b0, int nblk, hipStream_t st)
+{
+    GuardArgs g{};
+    g.blocks = c->d_blocks;
+    g.faces = c->d_faces;
+    g.b0 = b0;
+    g.nc = c->ncell;
+    g.U = U;
+    hipError_t e = launch_fill_guards(g, c->prm.ndim, nblk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "guard launch");
+    return HYDRO_OK;
+}
+
+// One stage in the configured form.  In per-block form Us must be writable
+// (its guards are materialised block by block).
+int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const double *Us, double *Uout,
+                  hipStream_t st)
+{
+    StageArgs a = stage_args(c, s, dt, Un, Us, Uout);
+    if (c->tune.mode == HYDRO_MODE_PERBLOCK) {
+        for (int b = 0; b < c->nblocks; ++b) {
+            int rc = enqueue_guards(c, const_cast<double *>(Us), b, 1, st);
+            if (rc) return rc;
+            a.items = c->d_items_pb + c->pb_start[b];
+            a.nitems = c->pb_start[b + 1] - c->pb_start[b];
+            hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, false, a.nitems, st);
+            if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+        }
+        return HYDRO_OK;
+    }
+    hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, true, persistent_grid(c), st);
+    if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+    return HYDRO_OK;
+}
+
+// Stage buffers: RK2 U -> B0 -> U ; RK3 U -> B0 -> B1 -> U.  The final stage
+// writes U in place (it reads U^n only at the cell it writes).
+int enqueue_step(hydro_ctx *c, double *U, double *dt, int compute_dt, hipStream_t st)
+{
+    int rc;
+    if (compute_dt && (rc = enqueue_cfl(c, U, dt, st))) return rc;
+    const int S = c->prm.rk;
+    double *in = U;
+    for (int s = 1; s <= S; ++s) {
+        double *out = (s == S) ? U : c->d_buf[(s - 1) & 1];
+        if ((rc = enqueue_stage(c, s, dt, U, in, out, st))) return rc;
+        in = out;
+    }
+    return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
+                   int32_t nblocks, int64_t ncell_total)
+{
+    return check_problem(params, blocks, links, nblocks, ncell_total).empty() ? HYDRO_OK : HYDRO_EINVAL;
+}
+
+static thread_local std::string g_create_err;
+
+int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
+                 int32_t nblocks, int64_t ncell_total, void *stream, hydro_ctx_t **out)
+{
+    if (!out) return HYDRO_EINVAL;
+    *out = nullptr;
+    std::string why = check_problem(params, blocks, links, nblocks, ncell_total);
+    if (!why.empty()) {
+        g_create_err = why;
+        return HYDRO_EINVAL;
+    }
+    hydro_ctx *c = new hydro_ctx();
+    c->prm = *params;
+    c->nblocks = nblocks;
+    c->ncell = ncell_total;
+    c->nv = params->ndim + 2;
+    c->hb.assign(blocks, blocks + nblocks);
+    c->hl.assign(links, links + nblocks);
+    c->stream = (hipStream_t)stream;
+    auto bail = [&](int code) {
+        g_create_err = c->err;
+        hydro_destroy(c);
+        return code;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) { c->err = "no HIP device"; return bail(HYDRO_EHIP); }
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        c->err = "capture stream";
+        return bail(HYDRO_EHIP);
+    }
+    build_tables(c);
+    const size_t nb = std::max<int>(1, nblocks);
+    if (hipMalloc(&c->d_blocks, sizeof(DevBlock) * nb) != hipSuccess ||
+        hipMalloc(&c->d_faces, sizeof(FaceSrc) * nb * 6) != hipSuccess ||
+        hipMalloc(&c->d_nbad, sizeof(unsigned long long)) != hipSuccess) {
+        c->err = "device tables";
+        return bail(HYDRO_ENOMEM);
+    }
+    if (nblocks > 0) {
+        if (hipMemcpy(c->d_blocks, c->h_dev.data(), sizeof(DevBlock) * nblocks, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->d_faces, c->h_faces.data(), sizeof(FaceSrc) * nblocks * 6, hipMemcpyHostToDevice) != hipSuccess) {
+            c->err = "table upload";
+            return bail(HYDRO_EHIP);
+        }
+    }
+    if (hipMemset(c->d_nbad, 0, sizeof(unsigned long long)) != hipSuccess) { c->err = "memset"; return bail(HYDRO_EHIP); }
+    const size_t sbytes = sizeof(double) * (size_t)c->nv * (size_t)std::max<int64_t>(1, ncell_total);
+    const int nbuf = (params->rk == 3) ? 2 : 1;
+    for (int q = 0; q < nbuf; ++q)
+        if (hipMalloc(&c->d_buf[q], sbytes) != hipSuccess) { c->err = "stage buffers"; return bail(HYDRO_ENOMEM); }
+    // default tuning: the tile with the best lane use (ties: larger), persistent, graph
+    double best = -1.0;
+    int tbest = 0;
+    for (int t = 0; t < 3; ++t) {
+        const int TX = tile_x(t), TY = tile_y(t);
+        double used = 0.0, paid = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            const auto &B = blocks[b];
+            used += (double)B.nx * B.ny;
+            paid += (double)((B.nx + TX - 1) / TX) * TX * ((B.ny + TY - 1) / TY) * TY;
+        }
+        const double u = paid > 0 ? used / paid : 1.0;
+        if (u >= best - 1e-12) { best = u; tbest = t; }
+    }
+    c->tune.mode = HYDRO_MODE_PERSISTENT;
+    c->tune.tile = tbest;
+    c->tune.grid = 0;
+    c->tune.zchunk = 0;
+    c->tune.use_graph = 1;
+    c->tune.xcd = 0;
+    int rc = upload_items(c);
+    if (rc) return bail(rc);
+    *out = c;
+    return HYDRO_OK;
+}
+
+int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
+{
+    if (!c || !t) return HYDRO_EINVAL;
+    if (t->mode != HYDRO_MODE_PERSISTENT && t->mode != HYDRO_MODE_PERBLOCK) return fail(c, HYDRO_EINVAL, "mode");
+    if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0) return fail(c, HYDRO_EINVAL, "tuning range");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->tune = *t;
+    return upload_items(c);
+}
+
+int hydro_get_tuning(hydro_ctx_t *c, hydro_tuning_t *t)
+{
+    if (!c || !t) return HYDRO_EINVAL;
+    *t = c->tune;
+    return HYDRO_OK;
+}
+
+int hydro_fill_guards(hydro_ctx_t *c, double *U)
+{
+    if (!c || !U) return HYDRO_EINVAL;
+    return enqueue_guards(c, U, 0, c->nblocks, c->stream);
+}
+
+int hydro_cfl_dt(hydro_ctx_t *c, const double *U, double *dt_dev)
+{
+    if (!c || !U || !dt_dev) return fail(c, HYDRO_EINVAL, "null pointer");
+    if (c->nitems == 0) return fail(c, HYDRO_EINVAL, "no cells");
+    return enqueue_cfl(c, U, dt_dev, c->stream);
+}
+
+int hydro_rk_stage(hydro_ctx_t *c, int32_t stage, const double *dt_dev, const double *Un, const double *Us,
+                   double *Uout)
+{
+    if (!c || !dt_dev || !Un || !Us || !Uout) return fail(c, HYDRO_EINVAL, "null pointer");
+    if (stage < 1 || stage > c->prm.rk) return fail(c, HYDRO_EINVAL, "stage out of range");
+    if (Uout == Us) return fail(c, HYDRO_EINVAL, "Uout aliases Us");
+    return enqueue_stage(c, stage, dt_dev, Un, Us, Uout, c->stream);
+}
+
+int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
+{
+    if (!c || !U || !dt_dev) return fail(c, HYDRO_EINVAL, "null pointer");
+    if (c->nitems == 0) return HYDRO_OK;
+    if (!c->tune.use_graph || c->tune.mode == HYDRO_MODE_PERBLOCK)
+        return enqueue_step(c, U, dt_dev, compute_dt, c->stream);
+    const int cdt = compute_dt ? 1 : 0;
+    if (!c->gexec || c->g_U != U || c->g_dt != dt_dev || c->g_cdt != cdt) {
+        drop_graph(c);
+        HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(c, U, dt_dev, cdt, c->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "end capture");
+        c->graph = g;
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(c);
+            return hip_fail(c, e, "graph instantiate");
+        }
+        c->g_U = U;
+        c->g_dt = dt_dev;
+        c->g_cdt = cdt;
+    }
+    HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+    return HYDRO_OK;
+}
+
+int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const double *gUnext, double *gUn)
+{
+    if (!c || !Un || !dt_dev || !gUnext || !gUn) return fail(c, HYDRO_EINVAL, "null pointer");
+    return fail(c, HYDRO_EINVAL, "adjoint not available in this build");
+}
+
+int hydro_status(hydro_ctx_t *c, int64_t *n_nonphys)
+{
+    if (!c) return HYDRO_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    unsigned long long n = 0;
+    HIP_TRY(c, hipMemcpy(&n, c->d_nbad, sizeof(n), hipMemcpyDeviceToHost));
+    if (n) HIP_TRY(c, hipMemset(c->d_nbad, 0, sizeof(n)));
+    if (n_nonphys) *n_nonphys = (int64_t)n;
+    if (n) return fail(c, HYDRO_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN) met " + std::to_string(n) + " times");
+    return HYDRO_OK;
+}
+
+const char *hydro_last_error(hydro_ctx_t *c)
+{
+    if (!c) return g_create_err.c_str();
+    return c->err.c_str();
+}
+
+void hydro_destroy(hydro_ctx_t *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    drop_graph(c);
+    (void)hipFree(c->d_blocks);
+    (void)hipFree(c->d_faces);
+    (void)hipFree(c->d_items);
+    (void)hipFree(c->d_items_pb);
+    (void)hipFree(c->d_buf[0]);
+    (void)hipFree(c->d_buf[1]);
+    (void)hipFree(c->d_partial);
+    (void)hipFree(c->d_nbad);
+    (void)hipFree(c->d_vjp);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+}
+
+}  // extern "C"

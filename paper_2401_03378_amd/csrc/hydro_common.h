@@ -1,0 +1,252 @@
+// Device-side building blocks of the FP64 Euler step for gfx950.
+//
+// Point-wise pieces of the method (the paper's intra-stage chain calcLims ->
+// calcFlux -> updSoln -> calcEos, Algorithm "Intra stage calculations for
+// Spark"): ideal-gas EOS, MC-limited PLM (van Leer 1977), WENO5-JS (Jiang &
+// Shu 1996), HLLC with Davis wave speeds (Toro 2009, Sec. 10.4).  Every
+// expression is written in the evaluation order the library fixes for
+// bit-reproducibility; the file is compiled with -ffp-contract=off, so an
+// fma occurs only where fma() is written.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hydro {
+
+constexpr int kPLM = 0;
+constexpr int kWENO = 1;
+
+// Geometry of one block as the kernels see it.
+struct DevBlock {
+    int64_t off;            // first padded cell in a variable plane
+    int32_t nx, ny, nz, ng;
+    int32_t px, py;         // padded x and y extents
+    int32_t gz;             // z guard width (ng in 3D, 0 in 2D)
+    int32_t pad;
+};
+
+// Where the guard layers of one block face are gathered from: the source
+// block's padded geometry and the map pos -> A + B*pos of the coordinate
+// along the face normal (neighbour interior, periodic wrap, or outflow copy).
+struct FaceSrc {
+    int64_t off;
+    int32_t px, py;
+    int32_t A, B;
+};
+
+// A work item: an xy tile of one block over a range of z planes.
+struct WorkItem {
+    int32_t block;
+    int32_t xy;      // x0 | y0 << 16
+    int32_t z;       // z0 | nz << 16
+    int32_t cost;
+};
+
+struct Consts {
+    double gamma, g1, ig1;
+};
+
+__device__ __forceinline__ double dmin(double a, double b) { return (a <= b) ? a : b; }
+__device__ __forceinline__ double dmax(double a, double b) { return (a >= b) ? a : b; }
+
+__device__ __forceinline__ int64_t cell_at(const DevBlock &B, int i, int j, int k)
+{
+    return B.off + ((int64_t)(k + B.gz) * B.py + (j + B.ng)) * B.px + (i + B.ng);
+}
+
+// Cell index of (i,j,k) where at most the coordinate along D lies outside
+// the block: a face guard is mapped onto the cell it is a copy of.
+template <int D, bool GATHER>
+__device__ __forceinline__ int64_t src_cell(const DevBlock &B, const FaceSrc *F, int i, int j, int k)
+{
+    if constexpr (!GATHER) {
+        return cell_at(B, i, j, k);
+    } else {
+        const int pos = (D == 0) ? i : ((D == 1) ? j : k);
+        const int n = (D == 0) ? B.nx : ((D == 1) ? B.ny : B.nz);
+        if (pos >= 0 && pos < n) return cell_at(B, i, j, k);
+        const FaceSrc f = F[2 * D + (pos < 0 ? 0 : 1)];
+        const int sp = f.A + f.B * pos;
+        int si = i, sj = j, sk = k;
+        if (D == 0) si = sp;
+        if (D == 1) sj = sp;
+        if (D == 2) sk = sp;
+        return f.off + ((int64_t)(sk + B.gz) * f.py + (sj + B.ng)) * f.px + (si + B.ng);
+    }
+}
+
+template <int NDIM>
+__device__ __forceinline__ void load_cons(const double *__restrict__ U, int64_t nc, int64_t ci, double (&u)[5])
+{
+#pragma unroll
+    for (int v = 0; v < NDIM + 2; ++v) u[v] = U[v * nc + ci];
+}
+
+// Conserved -> primitive (rho, u_x, u_y, u_z, p); returns true if not
+// (rho > 0 and p > 0).
+template <int NDIM>
+__device__ __forceinline__ bool eos(const double (&u)[5], double (&w)[5], double g1)
+{
+    const double r = 1.0 / u[0];
+    w[0] = u[0];
+    w[1] = u[1] * r;
+    w[2] = u[2] * r;
+    double ke;
+    if constexpr (NDIM == 3) {
+        w[3] = u[3] * r;
+        ke = 0.5 * ((u[1] * w[1] + u[2] * w[2]) + u[3] * w[3]);
+    } else {
+        w[3] = 0.0;
+        ke = 0.5 * (u[1] * w[1] + u[2] * w[2]);
+    }
+    w[4] = g1 * (u[NDIM + 1] - ke);
+    return !(w[0] > 0.0 && w[4] > 0.0);
+}
+
+// MC-limited linear reconstruction: left-face (qm) and right-face (qp)
+// values of the middle cell of (qa, q0, qb).
+__device__ __forceinline__ void plm(double qa, double q0, double qb, double &qm, double &qp)
+{
+    const double dm = q0 - qa, dp = qb - q0;
+    double s = 0.0;
+    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
+        const double a = 0.5 * (dm + dp);
+        const double aa = fabs(a), m2 = 2.0 * fabs(dm), p2 = 2.0 * fabs(dp);
+        const double lim = dmin(aa, dmin(m2, p2));
+        s = copysign(lim, a);
+    }
+    qp = q0 + 0.5 * s;
+    qm = q0 - 0.5 * s;
+}
+
+// WENO5-JS on (a,b,c,d,e) = q_{i-2..i+2}; both faces share beta_k.
+__device__ __forceinline__ void weno5(double a, double b, double c, double d, double e, double &qm, double &qp)
+{
+    const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
+    double t, w;
+    t = (a - 2.0 * b) + c;
+    w = (a - 4.0 * b) + 3.0 * c;
+    const double b0 = k13 * (t * t) + 0.25 * (w * w);
+    t = (b - 2.0 * c) + d;
+    w = b - d;
+    const double b1 = k13 * (t * t) + 0.25 * (w * w);
+    t = (c - 2.0 * d) + e;
+    w = (3.0 * c - 4.0 * d) + e;
+    const double b2 = k13 * (t * t) + 0.25 * (w * w);
+    const double o0 = 1.0 / ((eps + b0) * (eps + b0));
+    const double o1 = 1.0 / ((eps + b1) * (eps + b1));
+    const double o2 = 1.0 / ((eps + b2) * (eps + b2));
+    {
+        const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * k6;
+        const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;
+        const double p2 = ((2.0 * c + 5.0 * d) - e) * k6;
+        const double a0 = 0.1 * o0, a1 = 0.6 * o1, a2 = 0.3 * o2;
+        qp = ((a0 * p0 + a1 * p1) + a2 * p2) / ((a0 + a1) + a2);
+    }
+    {
+        const double p0 = ((2.0 * e - 7.0 * d) + 11.0 * c) * k6;
+        const double p1 = ((-d + 5.0 * c) + 2.0 * b) * k6;
+        const double p2 = ((2.0 * c + 5.0 * b) - a) * k6;
+        const double a0 = 0.1 * o2, a1 = 0.6 * o1, a2 = 0.3 * o0;
+        qm = ((a0 * p0 + a1 * p1) + a2 * p2) / ((a0 + a1) + a2);
+    }
+}
+
+// Reconstruct all primitives of one cell along a line; s[c][v] is the
+// stencil (2R+1 cells).  Applies the positivity fallback (both faces become
+// the cell value when either face has non-positive density or pressure).
+// Returns true if the fallback fired.
+template <int NDIM, int RECON, int S>
+__device__ __forceinline__ bool recon_cell(const double (&s)[S][5], double (&qm)[5], double (&qp)[5])
+{
+    constexpr int R = (RECON == kWENO) ? 2 : 1;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (NDIM == 2 && v == 3) { qm[v] = 0.0; qp[v] = 0.0; continue; }
+        if constexpr (RECON == kWENO)
+            weno5(s[R - 2][v], s[R - 1][v], s[R][v], s[R + 1][v], s[R + 2][v], qm[v], qp[v]);
+        else
+            plm(s[R - 1][v], s[R][v], s[R + 1][v], qm[v], qp[v]);
+    }
+    const bool fb = !(qm[0] > 0.0 && qm[4] > 0.0) || !(qp[0] > 0.0 && qp[4] > 0.0);
+    if (fb) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) { qm[v] = s[R][v]; qp[v] = s[R][v]; }
+    }
+    return fb;
+}
+
+// Face state -> conserved U, normal flux F (direction N), 1/rho, sound speed.
+template <int NDIM, int N>
+__device__ __forceinline__ void state_flux(const double (&w)[5], double (&u)[5], double (&f)[5], double &r,
+                                           double &c, const Consts &K)
+{
+    const double rho = w[0], p = w[4], un = w[1 + N];
+    double ke;
+    if constexpr (NDIM == 3)
+        ke = 0.5 * (rho * ((w[1] * w[1] + w[2] * w[2]) + w[3] * w[3]));
+    else
+        ke = 0.5 * (rho * (w[1] * w[1] + w[2] * w[2]));
+    const double E = p * K.ig1 + ke;
+    u[0] = rho;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) u[1 + d] = rho * w[1 + d];
+    u[NDIM + 1] = E;
+    const double fr = rho * un;
+    f[0] = fr;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) f[1 + d] = (d == N) ? (fr * un) + p : fr * w[1 + d];
+    f[NDIM + 1] = (E + p) * un;
+    r = 1.0 / rho;
+    c = sqrt((K.gamma * p) * r);
+}
+
+// Flux of the HLLC star region on side K: F*_K = F_K + S_K (U*_K - U_K).
+template <int NDIM, int N>
+__device__ __forceinline__ void star_flux(const double (&W)[5], const double (&UK)[5], const double (&FK)[5],
+                                          double SK, double mK, double rK, double Ss, double (&F)[5])
+{
+    constexpr int NV = NDIM + 2;
+    const double uK = W[1 + N];
+    const double chi = mK / (SK - Ss);
+    double Us[5];
+    Us[0] = chi;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) Us[1 + d] = (d == N) ? chi * Ss : chi * W[1 + d];
+    Us[NV - 1] = chi * (UK[NV - 1] * rK + (Ss - uK) * (Ss + W[4] / mK));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = fma(SK, (Us[v] - UK[v]), FK[v]);
+}
+
+// HLLC flux at a face normal to N from left/right primitive states, with
+// Davis bounds S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R)
+// and the contact speed S*.  Region: S_L >= 0 -> F_L; S* >= 0 -> F*_L;
+// S_R > 0 -> F*_R; else F_R.  Returns true if either state is non-physical.
+template <int NDIM, int N>
+__device__ __forceinline__ bool hllc(const double (&WL)[5], const double (&WR)[5], double (&F)[5], const Consts &K)
+{
+    constexpr int NV = NDIM + 2;
+    const bool bad = !(WL[0] > 0.0 && WL[4] > 0.0) || !(WR[0] > 0.0 && WR[4] > 0.0);
+    double UL[5], UR[5], FL[5], FR[5], rL, rR, cL, cR;
+    state_flux<NDIM, N>(WL, UL, FL, rL, cL, K);
+    state_flux<NDIM, N>(WR, UR, FR, rR, cR, K);
+    const double uL = WL[1 + N], uR = WR[1 + N];
+    const double SL = dmin(uL - cL, uR - cR);
+    const double SR = dmax(uL + cL, uR + cR);
+    const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
+    const double Ss = ((WR[4] - WL[4]) + (mL * uL - mR * uR)) / (mL - mR);
+    if (SL >= 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = FL[v];
+    } else if (Ss >= 0.0) {
+        star_flux<NDIM, N>(WL, UL, FL, SL, mL, rL, Ss, F);
+    } else if (SR > 0.0) {
+        star_flux<NDIM, N>(WR, UR, FR, SR, mR, rR, Ss, F);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = FR[v];
+    }
+    return bad;
+}
+
+}  // namespace hydro

@@ -1,0 +1,414 @@
+// Forward kernels of the FP64 Euler step on gfx950.
+//
+//  k_stage      fused stage: guard gather + EOS + reconstruction + HLLC +
+//               flux difference + SSP-RK combine, one launch for all blocks
+//               (the paper's per-stage block loop with the intra-stage chain
+//               calcLims -> calcFlux -> updSoln -> calcEos, Sec. 4.2).
+//  k_cfl_*      CFL time step: per-workgroup max of the wave-speed sum,
+//               then a one-workgroup reduction to dt on the device.
+//  k_fill_guards  materialised guard fill (the listing's fill_guardcells)
+//               for callers that want guards in the array, and for the
+//               plain per-block launch form.
+//
+// Work decomposition of k_stage.  A work item is an xy tile (TX x TY cells)
+// of one block over a run of z planes.  The workgroup marches through the
+// planes: each thread owns one column and keeps the primitive variables of a
+// (2R+1)-cell window along z in registers, so z-faces are reconstructed and
+// solved once and the flux of the lower face is carried to the next plane.
+// The current plane, with its x and y halo of R+1 cells, is staged in LDS as
+// primitives; x and y reconstruction read their stencils from there.  Guard
+// cells are never read from the state array: a halo cell outside the block
+// is gathered from the cell it is a copy of (neighbour interior, periodic
+// wrap, outflow copy).  A persistent grid walks the work list with a fixed
+// stride.
+#include "hydro_kernels.h"
+
+namespace hydro {
+
+template <int NDIM, int RECON, int TX, int TY, bool GATHER>
+__global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
+{
+    constexpr int R = (RECON == kWENO) ? 2 : 1;
+    constexpr int H = R + 1;
+    constexpr int NV = NDIM + 2;
+    constexpr int LX = TX + 2 * H, LY = TY + 2 * H;
+    constexpr int NT = TX * TY;
+    constexpr int NW = 2 * R + 1;   // z window
+    __shared__ double sW[5][LY][LX];
+    __shared__ double sQx[5][TY][TX + 1];
+    __shared__ double sQy[5][TY + 1][TX];
+    __shared__ double sFx[NV][TY][TX + 1];
+    __shared__ double sFy[NV][TY + 1][TX];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int64_t nc = A.nc;
+    const Consts K{A.gamma, A.g1, A.ig1};
+    const double dt = *A.dt;
+    bool bad = false;
+
+    for (int w = blockIdx.x; w < A.nitems; w += gridDim.x) {
+        const WorkItem it = A.items[w];
+        const DevBlock B = A.blocks[it.block];
+        const FaceSrc *F6 = A.faces + 6 * (int64_t)it.block;
+        const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
+        const int z0 = it.z & 0xffff, nzc = it.z >> 16;
+        const int wx = min(TX, B.nx - x0), wy = min(TY, B.ny - y0);
+        const bool own = (tx < wx) && (ty < wy);
+        const int i = x0 + tx, j = y0 + ty;
+        const int nhalo = 2 * H * (wx + wy);
+        const int nextra = 2 * (wx + wy);
+
+        double zw[NW][5];     // primitives of cells k+1-R .. k+1+R along z
+        double qpz[5];        // right-face state of cell k (z)
+        double Flo[5];        // z flux at k-1/2
+        if constexpr (NDIM == 3) {
+            if (own) {
+                double Wt[NW + 1][5];
+#pragma unroll
+                for (int c = 0; c < NW + 1; ++c) {
+                    double u[5];
+                    load_cons<NDIM>(A.Us, nc, src_cell<2, GATHER>(B, F6, i, j, z0 - H + c), u);
+                    bad |= eos<NDIM>(u, Wt[c], K.g1);
+                }
+                double s0[NW][5], s1[NW][5];
+#pragma unroll
+                for (int c = 0; c < NW; ++c)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) { s0[c][v] = Wt[c][v]; s1[c][v] = Wt[c + 1][v]; }
+                double qa[5], qb[5], qm[5];
+                recon_cell<NDIM, RECON>(s0, qa, qpz);      // cell z0-1: keep its right face
+                recon_cell<NDIM, RECON>(s1, qm, qb);       // cell z0
+                bad |= hllc<NDIM, 2>(qpz, qm, Flo, K);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qpz[v] = qb[v];
+#pragma unroll
+                for (int c = 0; c < NW - 1; ++c)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) zw[c][v] = Wt[c + 2][v];
+            }
+        }
+
+        for (int kk = 0; kk < nzc; ++kk) {
+            const int k = z0 + kk;
+            double Dz[5];
+            if (own) {
+                if constexpr (NDIM == 3) {
+                    double u[5];
+                    load_cons<NDIM>(A.Us, nc, src_cell<2, GATHER>(B, F6, i, j, k + H), u);
+                    bad |= eos<NDIM>(u, zw[NW - 1], K.g1);
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = zw[R - 1][v];
+                    double qm[5], qp[5], Fhi[5];
+                    recon_cell<NDIM, RECON>(zw, qm, qp);   // cell k+1
+                    bad |= hllc<NDIM, 2>(qpz, qm, Fhi, K);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) { Dz[v] = Fhi[v] - Flo[v]; Flo[v] = Fhi[v]; }
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) qpz[v] = qp[v];
+#pragma unroll
+                    for (int c = 0; c < NW - 1; ++c)
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) zw[c][v] = zw[c + 1][v];
+                } else {
+                    double u[5], wv[5];
+                    load_cons<NDIM>(A.Us, nc, cell_at(B, i, j, k), u);
+                    bad |= eos<NDIM>(u, wv, K.g1);
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = wv[v];
+                }
+            }
+            // x and y halo of plane k
+            for (int e = tid; e < nhalo; e += NT) {
+                int li, lj;
+                int64_t ci;
+                if (e < 2 * H * wy) {
+                    const int row = e / (2 * H), c = e % (2 * H);
+                    const int off = (c < H) ? c - H : wx + (c - H);   // -H..-1, wx..wx+H-1
+                    li = off + H;
+                    lj = row + H;
+                    ci = src_cell<0, GATHER>(B, F6, x0 + off, y0 + row, k);
+                } else {
+                    const int e2 = e - 2 * H * wy;
+                    const int c = e2 / wx, col = e2 % wx;
+                    const int off = (c < H) ? c - H : wy + (c - H);
+                    li = col + H;
+                    lj = off + H;
+                    ci = src_cell<1, GATHER>(B, F6, x0 + col, y0 + off, k);
+                }
+                double u[5], wv[5];
+                load_cons<NDIM>(A.Us, nc, ci, u);
+                bad |= eos<NDIM>(u, wv, K.g1);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sW[v][lj][li] = wv[v];
+            }
+            __syncthreads();
+
+            // x and y reconstruction: own cells, then the cells just outside the tile
+            double qmx[5], qmy[5], qme[5];
+            if (own) {
+                double s[NW][5], qp[5];
+#pragma unroll
+                for (int c = 0; c < NW; ++c)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) s[c][v] = sW[v][ty + H][tx + H - R + c];
+                recon_cell<NDIM, RECON>(s, qmx, qp);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sQx[v][ty][tx + 1] = qp[v];
+#pragma unroll
+                for (int c = 0; c < NW; ++c)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) s[c][v] = sW[v][ty + H - R + c][tx + H];
+                recon_cell<NDIM, RECON>(s, qmy, qp);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sQy[v][ty + 1][tx] = qp[v];
+            }
+            int etype = -1, epos = 0;
+            if (tid < nextra) {
+                double s[NW][5], qm[5], qp[5];
+                int e = tid;
+                if (e < 2 * wy) {          // x: cell -1 (type 0) or cell wx (type 1) of row epos
+                    etype = (e < wy) ? 0 : 1;
+                    epos = (e < wy) ? e : e - wy;
+                    const int cx = (etype == 0) ? -1 : wx;
+#pragma unroll
+                    for (int c = 0; c < NW; ++c)
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) s[c][v] = sW[v][epos + H][cx + H - R + c];
+                } else {                   // y: cell -1 (type 2) or cell wy (type 3) of column epos
+                    e -= 2 * wy;
+                    etype = (e < wx) ? 2 : 3;
+                    epos = (e < wx) ? e : e - wx;
+                    const int cy = (etype == 2) ? -1 : wy;
+#pragma unroll
+                    for (int c = 0; c < NW; ++c)
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) s[c][v] = sW[v][cy + H - R + c][epos + H];
+                }
+                recon_cell<NDIM, RECON>(s, qm, qp);
+                if (etype == 0) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) sQx[v][epos][0] = qp[v];
+                } else if (etype == 2) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) sQy[v][0][epos] = qp[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) qme[v] = qm[v];
+                }
+            }
+            __syncthreads();
+
+            // Riemann problems at the faces
+            if (own) {
+                double WL[5], Fv[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) WL[v] = sQx[v][ty][tx];
+                bad |= hllc<NDIM, 0>(WL, qmx, Fv, K);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sFx[v][ty][tx] = Fv[v];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) WL[v] = sQy[v][ty][tx];
+                bad |= hllc<NDIM, 1>(WL, qmy, Fv, K);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sFy[v][ty][tx] = Fv[v];
+            }
+            if (etype == 1) {
+                double WL[5], Fv[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) WL[v] = sQx[v][epos][wx];
+                bad |= hllc<NDIM, 0>(WL, qme, Fv, K);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sFx[v][epos][wx] = Fv[v];
+            } else if (etype == 3) {
+                double WL[5], Fv[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) WL[v] = sQy[v][wy][epos];
+                bad |= hllc<NDIM, 1>(WL, qme, Fv, K);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sFy[v][wy][epos] = Fv[v];
+            }
+            __syncthreads();
+
+            // flux differences and the SSP-RK combination
+            if (own) {
+                const int64_t ci = cell_at(B, i, j, k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double Dx = sFx[v][ty][tx + 1] - sFx[v][ty][tx];
+                    const double Dy = sFy[v][ty + 1][tx] - sFy[v][ty][tx];
+                    double acc = Dx * A.idx + Dy * A.idy;
+                    if constexpr (NDIM == 3) acc = acc + Dz[v] * A.idz;
+                    const double L = -acc;
+                    const double T = fma(dt, L, A.Us[v * nc + ci]);
+                    double out;
+                    if (A.stage == 1)
+                        out = T;
+                    else
+                        out = fma(A.b, T, A.a * A.Un[v * nc + ci]);
+                    A.Uout[v * nc + ci] = out;
+                }
+            }
+        }
+    }
+    if (bad) atomicAdd(A.nbad, 1ull);
+}
+
+// Per-workgroup maximum of the unsplit wave-speed sum over the interior
+// cells of its work items.
+template <int NDIM, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_cfl_partial(CflArgs A)
+{
+    constexpr int NT = TX * TY;
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    double m = 0.0;
+    bool bad = false;
+    for (int w = blockIdx.x; w < A.nitems; w += gridDim.x) {
+        const WorkItem it = A.items[w];
+        const DevBlock B = A.blocks[it.block];
+        const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
+        const int z0 = it.z & 0xffff, nzc = it.z >> 16;
+        const int i = x0 + tx, j = y0 + ty;
+        if (i < B.nx && j < B.ny) {
+            for (int k = z0; k < z0 + nzc; ++k) {
+                double u[5], wv[5];
+                load_cons<NDIM>(A.U, A.nc, cell_at(B, i, j, k), u);
+                bad |= eos<NDIM>(u, wv, A.g1);
+                const double r = 1.0 / u[0];
+                const double c = sqrt((A.gamma * wv[4]) * r);
+                double sig = ((fabs(wv[1]) + c) * A.idx) + ((fabs(wv[2]) + c) * A.idy);
+                if constexpr (NDIM == 3) sig = sig + ((fabs(wv[3]) + c) * A.idz);
+                m = (sig > m) ? sig : m;
+            }
+        }
+    }
+    for (int s = 32; s > 0; s >>= 1) {
+        const double o = __shfl_xor(m, s, 64);
+        m = (o > m) ? o : m;
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+        for (int q = 1; q < NT / 64; ++q) m = (red[q] > m) ? red[q] : m;
+        A.partial[blockIdx.x] = m;
+    }
+    if (bad) atomicAdd(A.nbad, 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_cfl_final(const double *__restrict__ partial, int n, double cfl,
+                                                   double *__restrict__ dt)
+{
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    double m = 0.0;
+    for (int q = tid; q < n; q += 256) m = (partial[q] > m) ? partial[q] : m;
+    for (int s = 32; s > 0; s >>= 1) {
+        const double o = __shfl_xor(m, s, 64);
+        m = (o > m) ? o : m;
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+        for (int q = 1; q < 4; ++q) m = (red[q] > m) ? red[q] : m;
+        *dt = cfl / m;
+    }
+}
+
+// Materialised guard fill for blocks [b0, b0 + gridDim.x / (2 NDIM)):
+// workgroup = (block, face); threads walk layers x transverse cells.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_fill_guards(GuardArgs A)
+{
+    const int b = A.b0 + blockIdx.x / (2 * NDIM);
+    const int f = blockIdx.x % (2 * NDIM);
+    const int d = f / 2, side = f % 2;
+    const DevBlock B = A.blocks[b];
+    const FaceSrc S = A.faces[6 * (int64_t)b + f];
+    const int n = (d == 0) ? B.nx : ((d == 1) ? B.ny : B.nz);
+    const int n1 = (d == 0) ? B.ny : B.nx;
+    const int n2 = (NDIM == 3) ? ((d == 2) ? B.ny : B.nz) : 1;
+    const int count = B.ng * n1 * n2;
+    for (int e = threadIdx.x; e < count; e += blockDim.x) {
+        const int l = e / (n1 * n2) + 1;
+        const int r = e % (n1 * n2);
+        const int e1 = r % n1, e2 = r / n1;
+        const int pos = (side == 0) ? -l : n - 1 + l;
+        const int sp = S.A + S.B * pos;
+        int g[3], s[3];
+        if (d == 0) { g[0] = pos; g[1] = e1; g[2] = e2; s[0] = sp; s[1] = e1; s[2] = e2; }
+        else if (d == 1) { g[0] = e1; g[1] = pos; g[2] = e2; s[0] = e1; s[1] = sp; s[2] = e2; }
+        else { g[0] = e1; g[1] = e2; g[2] = pos; s[0] = e1; s[1] = e2; s[2] = sp; }
+        const int64_t gi = cell_at(B, g[0], g[1], g[2]);
+        const int64_t si = S.off + ((int64_t)(s[2] + B.gz) * S.py + (s[1] + B.ng)) * S.px + (s[0] + B.ng);
+#pragma unroll
+        for (int v = 0; v < NDIM + 2; ++v) A.U[v * A.nc + gi] = A.U[v * A.nc + si];
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+template <int NDIM, int RECON, int TX, int TY, bool GATHER>
+static hipError_t launch_stage_t(const StageArgs &a, int grid, hipStream_t st)
+{
+    k_stage<NDIM, RECON, TX, TY, GATHER><<<grid, TX * TY, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <int NDIM, int RECON, bool GATHER>
+static hipError_t launch_stage_r(const StageArgs &a, int tile, int grid, hipStream_t st)
+{
+    switch (tile) {
+    case 0: return launch_stage_t<NDIM, RECON, 8, 8, GATHER>(a, grid, st);
+    case 1: return launch_stage_t<NDIM, RECON, 16, 8, GATHER>(a, grid, st);
+    default: return launch_stage_t<NDIM, RECON, 16, 16, GATHER>(a, grid, st);
+    }
+}
+
+hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, bool gather, int grid, hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    if (ndim == 3) {
+        if (recon == kWENO)
+            return gather ? launch_stage_r<3, kWENO, true>(a, tile, grid, st)
+                          : launch_stage_r<3, kWENO, false>(a, tile, grid, st);
+        return gather ? launch_stage_r<3, kPLM, true>(a, tile, grid, st)
+                      : launch_stage_r<3, kPLM, false>(a, tile, grid, st);
+    }
+    if (recon == kWENO)
+        return gather ? launch_stage_r<2, kWENO, true>(a, tile, grid, st)
+                      : launch_stage_r<2, kWENO, false>(a, tile, grid, st);
+    return gather ? launch_stage_r<2, kPLM, true>(a, tile, grid, st)
+                  : launch_stage_r<2, kPLM, false>(a, tile, grid, st);
+}
+
+template <int NDIM>
+static hipError_t launch_cfl_n(const CflArgs &a, int tile, int grid, hipStream_t st)
+{
+    switch (tile) {
+    case 0: k_cfl_partial<NDIM, 8, 8><<<grid, 64, 0, st>>>(a); break;
+    case 1: k_cfl_partial<NDIM, 16, 8><<<grid, 128, 0, st>>>(a); break;
+    default: k_cfl_partial<NDIM, 16, 16><<<grid, 256, 0, st>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl, double *dt, hipStream_t st)
+{
+    hipError_t e = (ndim == 3) ? launch_cfl_n<3>(a, tile, grid, st) : launch_cfl_n<2>(a, tile, grid, st);
+    if (e != hipSuccess) return e;
+    k_cfl_final<<<1, 256, 0, st>>>(a.partial, grid, cfl, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (ndim == 3)
+        k_fill_guards<3><<<nblk * 6, 256, 0, st>>>(a);
+    else
+        k_fill_guards<2><<<nblk * 4, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace hydro

@@ -1,0 +1,67 @@
+// Kernel argument blocks and launchers shared by the library's host code.
+#pragma once
+#include "hydro_common.h"
+
+namespace hydro {
+
+struct StageArgs {
+    const DevBlock *blocks;
+    const FaceSrc *faces;
+    const WorkItem *items;
+    int32_t nitems;
+    int32_t stage;              // 1-based SSP-RK stage
+    int64_t nc;                 // cells per variable plane
+    double gamma, g1, ig1;
+    double idx, idy, idz;
+    double a, b;                // U_out = b T + a U^n for stage >= 2
+    const double *dt;           // device scalar
+    const double *Un;
+    const double *Us;
+    double *Uout;
+    unsigned long long *nbad;
+};
+
+struct CflArgs {
+    const DevBlock *blocks;
+    const WorkItem *items;
+    int32_t nitems;
+    int64_t nc;
+    double gamma, g1, idx, idy, idz;
+    const double *U;
+    double *partial;
+    unsigned long long *nbad;
+};
+
+struct GuardArgs {
+    const DevBlock *blocks;
+    const FaceSrc *faces;
+    int32_t b0;
+    int64_t nc;
+    double *U;
+};
+
+struct VjpArgs {
+    const DevBlock *blocks;
+    const FaceSrc *faces;
+    const WorkItem *items;
+    int32_t nitems;
+    int32_t stage;
+    int64_t nc;
+    double gamma, g1, ig1;
+    double idx, idy, idz;
+    double a, b;
+    const double *dt;
+    const double *Us;          // stage input (forward state)
+    const double *gOut;        // cotangent of the stage output
+    double *gUs;               // cotangent of the stage input (interior), written
+    double *gUn;               // a_s gOut accumulated here (may be null for stage 1)
+    double *gHalo;             // per-item halo cotangent scratch
+    const int64_t *haloBase;   // per item: first slot in gHalo
+    unsigned long long *nbad;
+};
+
+hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, bool gather, int grid, hipStream_t st);
+hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl, double *dt, hipStream_t st);
+hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st);
+
+}  // namespace hydro

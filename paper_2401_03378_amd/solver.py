@@ -1,0 +1,125 @@
+"""Python front end of the GPU step: device memory and streams from PyTorch,
+every computation in libhydro's HIP kernels (through the C ABI)."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _hip
+from ._hip import HydroError, Tuning
+
+
+def _ptr(t):
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """A problem bound to one GPU and one stream.
+
+    prob: a workload description (ndim, recon, rk, gamma, cfl, dx, dy, dz,
+    blocks, links, ncell).  State tensors are float64 (nvar, ncell) on the
+    solver's device."""
+
+    def __init__(self, prob, device="cuda", stream=None, tuning=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the hydro step runs only in its HIP kernels")
+        self.prob = prob
+        self.device = torch.device(device)
+        self.nvar = int(prob.ndim) + 2
+        self.ncell = int(prob.ncell)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._L = _hip.lib()
+        P, B, L, nb = _hip.tables(prob)
+        ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self._L.hydro_create(C.byref(P), B, L, nb, self.ncell,
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if rc != _hip.HYDRO_OK:
+            raise HydroError(rc, self._L.hydro_last_error(None).decode())
+        self.ctx = ctx
+        self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)
+        if tuning:
+            self.set_tuning(**tuning)
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, rc):
+        if rc != _hip.HYDRO_OK:
+            raise HydroError(rc, self._L.hydro_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self._L.hydro_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def to_device(self, U):
+        return torch.as_tensor(np.ascontiguousarray(U), dtype=torch.float64).to(self.device)
+
+    def tuning(self):
+        t = Tuning()
+        self._check(self._L.hydro_get_tuning(self.ctx, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        cur = self.tuning()
+        cur.update(kw)
+        t = Tuning(**cur)
+        self._check(self._L.hydro_set_tuning(self.ctx, C.byref(t)))
+
+    # ------------------------------------------------------------ the method
+    def fill_guards(self, U):
+        self._check(self._L.hydro_fill_guards(self.ctx, _ptr(U)))
+
+    def cfl_dt(self, U, out=None):
+        out = self.dt if out is None else out
+        self._check(self._L.hydro_cfl_dt(self.ctx, _ptr(U), _ptr(out)))
+        return out
+
+    def rk_stage(self, stage, Un, Us, Uout, dt=None):
+        dt = self.dt if dt is None else dt
+        self._check(self._L.hydro_rk_stage(self.ctx, int(stage), _ptr(dt), _ptr(Un), _ptr(Us), _ptr(Uout)))
+
+    def step(self, U, dt=None):
+        """One step in place.  dt None: CFL dt (left in self.dt); a float or a
+        device tensor: that dt."""
+        if dt is None:
+            self._check(self._L.hydro_step(self.ctx, _ptr(U), _ptr(self.dt), 1))
+            return self.dt
+        if not torch.is_tensor(dt):
+            self.dt.fill_(float(dt))
+            dt = self.dt
+        self._check(self._L.hydro_step(self.ctx, _ptr(U), _ptr(dt), 0))
+        return dt
+
+    def run(self, U, nsteps, record_dt=True):
+        """nsteps CFL steps in place; returns the dts (device tensor)."""
+        dts = torch.empty(nsteps, dtype=torch.float64, device=self.device)
+        for n in range(nsteps):
+            self.step(U)
+            if record_dt:
+                dts[n:n + 1].copy_(self.dt)
+        return dts
+
+    def step_vjp(self, Un, gUnext, dt, gUn=None):
+        if not torch.is_tensor(dt):
+            d = torch.full((1,), float(dt), dtype=torch.float64, device=self.device)
+        else:
+            d = dt
+        gUn = torch.empty_like(Un) if gUn is None else gUn
+        self._check(self._L.hydro_step_vjp(self.ctx, _ptr(Un), _ptr(d), _ptr(gUnext), _ptr(gUn)))
+        return gUn
+
+    def status(self):
+        n = C.c_int64(0)
+        rc = self._L.hydro_status(self.ctx, C.byref(n))
+        if rc != _hip.HYDRO_OK:
+            raise HydroError(rc, self._L.hydro_last_error(self.ctx).decode())
+        return 0

@@ -252,14 +252,14 @@ def batched_uneven(nblocks=4096, fractions=(0.5, 0.4, 0.1), sizes=(8, 16, 32),
                    dx=1.0 / 32):
     """Independent periodic blocks of uneven sizes advanced together.
 
-    Counts per size are floor(f*nblocks) with the remainder given to the first
-    size; the size sequence is a seeded permutation and offsets follow it.  Per
+    Counts per size are floor(f*nblocks) for all but the last size, which
+    takes the remainder (4096 -> 2048, 1638, 410); the size sequence is a seeded permutation and offsets follow it.  Per
     cell, independently: rho = exp(0.3 N(0,1)), p = exp(0.3 N(0,1)),
     u_d = 0.3 c N(0,1) with c = sqrt(gamma p / rho); gamma = 5/3.
     """
     gamma = 5.0 / 3.0
-    counts = [int(math.floor(f * nblocks)) for f in fractions]
-    counts[0] += nblocks - sum(counts)
+    counts = [int(math.floor(f * nblocks)) for f in fractions[:-1]]
+    counts.append(nblocks - sum(counts))
     r_perm, r_field = _streams(seed, 2)
     seq = np.concatenate([np.full(c, s) for c, s in zip(counts, sizes)])
     seq = seq[r_perm.permutation(len(seq))]

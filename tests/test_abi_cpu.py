@@ -1,0 +1,73 @@
+"""The C-ABI library loads on a host without a GPU, exports every symbol the
+header declares, and its host-side validation rejects bad problems (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2401_03378_amd import _hip
+from paper_2401_03378_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hydro.h")).read()
+    return sorted(set(re.findall(r"\b(hydro_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("hydro_step", "hydro_rk_stage", "hydro_cfl_dt", "hydro_step_vjp", "hydro_create"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _hip.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert set(_hip.EXPORTS) <= set(_declared())
+
+
+def test_validate_accepts_workloads():
+    for p in (W.sod2d(N=32), W.random_blocks(3, 6, 3, seed=0, recon=1, rk=3),
+              W.batched_uneven(nblocks=16)):
+        assert _hip.validate(p) == _hip.HYDRO_OK
+
+
+def _mut(f):
+    p = W.random_blocks(3, 6, 2, seed=0)
+    f(p)
+    return _hip.validate(p)
+
+
+@pytest.mark.parametrize("f", [
+    lambda p: p.blocks["offset"].__setitem__(1, int(p.blocks["offset"][0]) + 5),
+    lambda p: p.blocks["offset"].__setitem__(0, -1),
+    lambda p: p.blocks["offset"].__setitem__(2, p.ncell),
+    lambda p: p.blocks["ng"].__setitem__(0, 1),
+    lambda p: p.blocks["nx"].__setitem__(0, 0),
+    lambda p: p.links["nbr"].__setitem__(0, [7, 9, -1, -1, -1, -1]),
+    lambda p: p.links["nbr"].__setitem__(0, [-3, -1, -1, -1, -1, -1]),
+    lambda p: setattr(p, "gamma", 1.0),
+    lambda p: setattr(p, "cfl", 0.0),
+    lambda p: setattr(p, "dx", -1.0),
+    lambda p: setattr(p, "rk", 4),
+    lambda p: setattr(p, "recon", 2),
+    lambda p: setattr(p, "ndim", 1),
+])
+def test_validate_rejects(f):
+    assert _mut(f) == _hip.HYDRO_EINVAL
+
+
+def test_validate_mismatched_faces_and_weno_guards():
+    blocks, ncell = W.make_table([(6, 6, 6), (6, 4, 6)], 2, 3)
+    links = np.zeros(2, dtype=W.LINK_DTYPE)
+    links["nbr"] = [1, 1, -2, -2, -2, -2]
+    p = W.random_blocks(3, 6, 2, seed=0)
+    p.blocks, p.links, p.ncell = blocks, links, ncell
+    assert _hip.validate(p) == _hip.HYDRO_EINVAL
+    q = W.random_blocks(3, 6, 2, seed=0, recon=W.WENO5, rk=3)
+    assert _hip.validate(q) == _hip.HYDRO_EINVAL

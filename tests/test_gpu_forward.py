@@ -1,0 +1,212 @@
+"""GPU forward path vs the CPU oracle, element by element (needs an MI355X).
+
+Every call goes through the C ABI (libhydro.so via ctypes); the oracle runs
+the same seeded inputs on the host.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2401_03378_amd import workloads as W
+from parity import assert_parity, field_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _solver(p, **tune):
+    from paper_2401_03378_amd.solver import Solver
+    return Solver(p, tuning=tune or None)
+
+
+def _gpu_run(p, nsteps, **tune):
+    S = _solver(p, **tune)
+    U = S.to_device(p.U0)
+    dts = S.run(U, nsteps)
+    S.status()
+    out = U.cpu().numpy(), dts.cpu().numpy()
+    S.close()
+    return out
+
+
+def _ora_run(p, nsteps):
+    U = p.U0.copy()
+    dts = O.run(p, U, nsteps)
+    return U, np.array(dts)
+
+
+SMALL = [
+    # ndim, recon, rk, n, ng, bc, NB
+    (2, 0, 2, 12, 2, "outflow", (2, 2, 1)),
+    (2, 0, 2, 16, 2, "periodic", (3, 2, 1)),
+    (2, 1, 3, 20, 3, "periodic", (2, 2, 1)),
+    (2, 1, 2, 9, 3, "outflow", (2, 3, 1)),
+    (3, 0, 2, 10, 2, "periodic", (2, 2, 2)),
+    (3, 0, 3, 8, 2, "outflow", (2, 1, 2)),
+    (3, 1, 3, 12, 3, "outflow", (2, 2, 2)),
+    (3, 1, 3, 16, 3, "periodic", (1, 2, 2)),
+    (3, 1, 2, 7, 4, "periodic", (2, 2, 1)),
+]
+
+
+@pytest.mark.parametrize("ndim,recon,rk,n,ng,bc,NB", SMALL)
+def test_parity_small_all_tiles(ndim, recon, rk, n, ng, bc, NB):
+    """Several tiles and a ragged tail per block; every tile shape and
+    z-chunking gives the oracle's result (and the same bits as each other)."""
+    p = W.random_blocks(ndim, n, ng, seed=3, recon=recon, rk=rk, bc=bc, NB=NB)
+    Uo, dto = _ora_run(p, 3)
+    first = None
+    for tile in (0, 1, 2):
+        for zchunk in ((0, 5) if ndim == 3 else (0,)):
+            Ug, dtg = _gpu_run(p, 3, tile=tile, zchunk=zchunk)
+            assert np.array_equal(dtg, dto), (tile, zchunk, dtg, dto)
+            assert_parity(p, Ug, Uo, f"tile {tile} zchunk {zchunk}")
+            if first is None:
+                first = Ug
+            else:
+                m = W.interior_mask(p.blocks, p.ncell, ndim)
+                assert np.array_equal(first[:, m], Ug[:, m])
+
+
+def test_sod_full_config():
+    p = W.config(0)
+    Uo, dto = _ora_run(p, p.nsteps)
+    Ug, dtg = _gpu_run(p, p.nsteps)
+    assert np.array_equal(dtg, dto)
+    errs = assert_parity(p, Ug, Uo, "sod2d")
+    print("sod2d field errors", errs)
+
+
+def test_sedov_full_config():
+    p = W.config(1)
+    Uo, dto = _ora_run(p, p.nsteps)
+    Ug, dtg = _gpu_run(p, p.nsteps)
+    np.testing.assert_array_equal(dtg, dto)
+    errs = assert_parity(p, Ug, Uo, "sedov3d")
+    print("sedov3d field errors", errs)
+
+
+def test_batched_full_size_two_steps():
+    p = W.config(2)
+    Uo, dto = _ora_run(p, 2)
+    Ug, dtg = _gpu_run(p, 2)
+    np.testing.assert_array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, "batched")
+
+
+def test_batched_subset_all_steps():
+    p = W.batched_uneven(nblocks=256, seed=1)
+    Uo, dto = _ora_run(p, 10)
+    Ug, dtg = _gpu_run(p, 10)
+    np.testing.assert_array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, "batched-256")
+
+
+def test_kh_full_config():
+    p = W.config(3)
+    Uo, dto = _ora_run(p, p.nsteps)
+    Ug, dtg = _gpu_run(p, p.nsteps)
+    np.testing.assert_array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, "kh2d")
+
+
+def test_turbulence_full_size_one_step():
+    p = W.config(4)
+    Uo, dto = _ora_run(p, 1)
+    Ug, dtg = _gpu_run(p, 1)
+    np.testing.assert_array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, "turb3d")
+
+
+def test_turbulence_small_all_steps():
+    p = W.turb3d(N=64, n=16, seed=2)
+    Uo, dto = _ora_run(p, 5)
+    Ug, dtg = _gpu_run(p, 5)
+    np.testing.assert_array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, "turb3d-64")
+
+
+@pytest.mark.parametrize("mode_kw", [dict(mode=1), dict(use_graph=0), dict(grid=37), dict(grid=256, xcd=1)])
+def test_launch_forms_bitwise_identical(mode_kw):
+    """Per-block launches, no graph, odd persistent grids and the XCD
+    placement all give the persistent graph-replayed result bit for bit."""
+    p = W.batched_uneven(nblocks=96, seed=4)
+    ref, dref = _gpu_run(p, 3)
+    Ug, dtg = _gpu_run(p, 3, **mode_kw)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    assert np.array_equal(dtg, dref)
+    assert np.array_equal(Ug[:, m], ref[:, m])
+
+
+def test_stage_and_dt_entry_points():
+    p = W.random_blocks(3, 10, 3, seed=5, recon=1, rk=3, bc="outflow")
+    S = _solver(p)
+    U = S.to_device(p.U0)
+    dt = S.cfl_dt(U)
+    assert float(dt.item()) == O.cfl_dt(p, p.U0)
+    B1 = U.clone()
+    B2 = U.clone()
+    U3 = U.clone()
+    S.rk_stage(1, U, U, B1)
+    S.rk_stage(2, U, B1, B2)
+    S.rk_stage(3, U, B2, U3)
+    ref = p.U0.copy()
+    O.step(p, ref, float(dt.item()))
+    assert_parity(p, U3.cpu().numpy(), ref, "stages")
+    Ustep = S.to_device(p.U0)
+    S.step(Ustep)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    assert np.array_equal(Ustep.cpu().numpy()[:, m], U3.cpu().numpy()[:, m])
+    S.close()
+
+
+def test_fill_guards_matches_oracle():
+    p = W.random_blocks(3, 6, 3, seed=6, bc="periodic", NB=(2, 1, 3))
+    S = _solver(p)
+    U = S.to_device(p.U0)
+    S.fill_guards(U)
+    ref = p.U0.copy()
+    O.fill_guards(p, ref)
+    got = U.cpu().numpy()
+    both_nan = np.isnan(got) & np.isnan(ref)
+    assert np.array_equal(got[~both_nan], ref[~both_nan]) and np.array_equal(np.isnan(got), np.isnan(ref))
+    S.close()
+
+
+def test_graph_replays_are_identical():
+    p = W.random_blocks(2, 16, 2, seed=7, NB=(3, 3, 1))
+    S = _solver(p)
+    U1 = S.to_device(p.U0)
+    for _ in range(4):
+        S.step(U1, 1e-4)
+    S.set_tuning(use_graph=0)
+    U2 = S.to_device(p.U0)
+    for _ in range(4):
+        S.step(U2, 1e-4)
+    m = W.interior_mask(p.blocks, p.ncell, 2)
+    assert np.array_equal(U1.cpu().numpy()[:, m], U2.cpu().numpy()[:, m])
+    S.close()
+
+
+def test_free_stream_gpu():
+    p = W.random_blocks(3, 8, 3, seed=0, recon=1, rk=2)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    for v, val in enumerate([1.3, 0.4, -0.7, 0.2, 2.9]):
+        p.U0[v, m] = val
+    Ug, _ = _gpu_run(p, 4)
+    assert np.array_equal(Ug[:, m], p.U0[:, m])
+
+
+def test_nonphysical_state_is_reported():
+    from paper_2401_03378_amd._hip import HydroError, HYDRO_ENONPHYS
+    p = W.random_blocks(3, 8, 2, seed=1)
+    m = np.flatnonzero(W.interior_mask(p.blocks, p.ncell, 3))
+    p.U0[4, m[11]] = -5.0
+    S = _solver(p)
+    U = S.to_device(p.U0)
+    S.step(U, 1e-4)
+    with pytest.raises(HydroError) as e:
+        S.status()
+    assert e.value.code == HYDRO_ENONPHYS
+    S.status()          # the count was reset
+    S.close()
