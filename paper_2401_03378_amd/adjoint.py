@@ -1,0 +1,122 @@
+"""Differentiation of the hydro step: a torch.autograd.Function per step and
+a checkpointed multi-step rollout.
+
+The gradient is taken with every dt held fixed (the dt sequence of the
+forward pass is recorded and replayed) and with the branches of the forward
+pass (limiter slopes, positivity fallback, Riemann-solver region); the
+per-step transpose is the library's hydro_step_vjp.
+
+Checkpointing: the forward rollout stores the state every k steps; the
+backward pass walks the segments in reverse, recomputes a segment's step
+inputs from its checkpoint, then applies the step VJPs in reverse.  Memory is
+(N/k + k) states instead of N.  The rollout logic is written against a small
+stepper interface (step / step_vjp / copy) so that it can be exercised with
+any implementation of a step.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class Tape:
+    """What a checkpointed forward rollout keeps: states every k steps and
+    every dt."""
+
+    def __init__(self, k):
+        self.k = k
+        self.checkpoints = {}   # step index -> state before that step
+        self.dts = []
+        self.recomputed_steps = 0
+
+
+def rollout(stepper, U0, nsteps, k, dts=None):
+    """Advance a copy of U0 by nsteps; returns (U_N, tape).  dts: optional
+    fixed time steps; otherwise each step takes its CFL dt (recorded)."""
+    if k < 1:
+        raise ValueError("checkpoint interval must be >= 1")
+    tape = Tape(k)
+    U = stepper.copy(U0)
+    for n in range(nsteps):
+        if n % k == 0:
+            tape.checkpoints[n] = stepper.copy(U)
+        dt = stepper.step(U, None if dts is None else dts[n])
+        tape.dts.append(float(dt))
+    return U, tape
+
+
+def rollout_vjp(stepper, tape, gUN):
+    """Cotangent of U0 given the cotangent of U_N, by segments in reverse."""
+    nsteps = len(tape.dts)
+    g = gUN
+    starts = sorted(tape.checkpoints)
+    for s0 in reversed(starts):
+        s1 = min(s0 + tape.k, nsteps)
+        # recompute the inputs of steps s0 .. s1-1
+        states = [stepper.copy(tape.checkpoints[s0])]
+        for n in range(s0, s1 - 1):
+            U = stepper.copy(states[-1])
+            stepper.step(U, tape.dts[n])
+            tape.recomputed_steps += 1
+            states.append(U)
+        for n in range(s1 - 1, s0 - 1, -1):
+            g = stepper.step_vjp(states[n - s0], g, tape.dts[n])
+    return g
+
+
+class TorchStepper:
+    """Stepper over a Solver (GPU tensors)."""
+
+    def __init__(self, solver):
+        self.S = solver
+
+    def copy(self, U):
+        return U.clone()
+
+    def step(self, U, dt=None):
+        d = self.S.step(U, dt)
+        return float(d.item()) if torch.is_tensor(d) else float(d)
+
+    def step_vjp(self, Un, g, dt):
+        return self.S.step_vjp(Un, g.contiguous(), dt)
+
+
+class HydroStep(torch.autograd.Function):
+    """U_{n+1} = step(U_n) at a given dt; backward = hydro_step_vjp."""
+
+    @staticmethod
+    def forward(ctx, U, dt, solver):
+        out = U.detach().clone()
+        solver.step(out, float(dt))
+        ctx.save_for_backward(U.detach())
+        ctx.dt = float(dt)
+        ctx.solver = solver
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (U,) = ctx.saved_tensors
+        return ctx.solver.step_vjp(U, g.contiguous(), ctx.dt), None, None
+
+
+class HydroRollout(torch.autograd.Function):
+    """U_N after nsteps CFL steps, with a checkpointed backward pass."""
+
+    @staticmethod
+    def forward(ctx, U0, solver, nsteps, k):
+        st = TorchStepper(solver)
+        UN, tape = rollout(st, U0.detach(), nsteps, k)
+        ctx.stepper = st
+        ctx.tape = tape
+        return UN
+
+    @staticmethod
+    def backward(ctx, g):
+        return rollout_vjp(ctx.stepper, ctx.tape, g.contiguous()), None, None, None
+
+
+def hydro_step(U, dt, solver):
+    return HydroStep.apply(U, dt, solver)
+
+
+def hydro_rollout(U0, solver, nsteps, k):
+    return HydroRollout.apply(U0, solver, nsteps, k)

@@ -18,16 +18,17 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-CACHE = os.path.join(HERE, "tuning_cache.json")
+CACHE = os.environ.get("HYDRO_TUNE_CACHE", os.path.join(HERE, "tuning_cache.json"))
 
 
-def signature(prob) -> str:
+def signature(prob, arch=None) -> str:
     b = np.ascontiguousarray(prob.blocks)
     h = hashlib.sha256(b.tobytes() + np.ascontiguousarray(prob.links).tobytes()).hexdigest()[:12]
-    try:
-        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    except Exception:
-        arch = "unknown"
+    if arch is None:
+        try:
+            arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        except Exception:
+            arch = "unknown"
     return f"{arch}|d{prob.ndim}|r{prob.recon}|rk{prob.rk}|nb{len(b)}|{h}"
 
 
@@ -78,7 +79,8 @@ def search(S, prob, nsteps=5, log=print):
     return best[1], results
 
 
-def tuned_or_search(S, prob, log=print, cache=CACHE):
+def tuned_or_search(S, prob, log=print, cache=None):
+    cache = cache or CACHE
     sig = signature(prob)
     db = {}
     if os.path.exists(cache):

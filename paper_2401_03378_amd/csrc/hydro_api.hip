@@ -44,9 +44,14 @@ struct hydro_ctx {
     const double *g_U = nullptr;
     const double *g_dt = nullptr;
     int g_cdt = -1;
-    // adjoint scratch
-    double *d_vjp = nullptr;
-    size_t vjp_bytes = 0;
+    // adjoint: line work lists per direction, 8x8 cell tiles, inverse links, scratch
+    WorkItem *d_lines[3] = {nullptr, nullptr, nullptr};
+    int nlines[3] = {0, 0, 0};
+    WorkItem *d_citems = nullptr;
+    int ncitems = 0;
+    int *d_inc_start = nullptr;
+    int4 *d_inc = nullptr;
+    double *d_vjp = nullptr;     // gW | gA | gB, each nvar x ncell
 };
 
 namespace {
@@ -360,6 +365,81 @@ int enqueue_step(hydro_ctx *c, double *U, double *dt, int compute_dt, hipStream_
     return HYDRO_OK;
 }
 
+// Work lists and tables of the adjoint (built on first use).
+int setup_vjp(hydro_ctx *c)
+{
+    if (c->d_vjp) return HYDRO_OK;
+    const int nd = c->prm.ndim;
+    // lines along each direction, grouped by 64 within a block
+    for (int d = 0; d < nd; ++d) {
+        std::vector<WorkItem> v;
+        for (int b = 0; b < c->nblocks; ++b) {
+            const hydro_block_t &B = c->hb[b];
+            const int n1 = (d == 0) ? B.ny : B.nx;
+            const int n2 = (nd == 3) ? ((d == 2) ? B.ny : B.nz) : 1;
+            const int nl = n1 * n2;
+            for (int l0 = 0; l0 < nl; l0 += 64) {
+                WorkItem w{};
+                w.block = b;
+                w.xy = l0;
+                w.z = std::min(64, nl - l0);
+                w.cost = 0;
+                v.push_back(w);
+            }
+        }
+        c->nlines[d] = (int)v.size();
+        HIP_TRY(c, hipMalloc(&c->d_lines[d], sizeof(WorkItem) * std::max<size_t>(1, v.size())));
+        if (!v.empty())
+            HIP_TRY(c, hipMemcpy(c->d_lines[d], v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
+    }
+    // cell tiles 8x8 over whole z columns
+    std::vector<WorkItem> ci;
+    for (int b = 0; b < c->nblocks; ++b) {
+        const hydro_block_t &B = c->hb[b];
+        const int nz = (nd == 3) ? B.nz : 1;
+        for (int y0 = 0; y0 < B.ny; y0 += 8)
+            for (int x0 = 0; x0 < B.nx; x0 += 8) {
+                WorkItem w{};
+                w.block = b;
+                w.xy = x0 | (y0 << 16);
+                w.z = 0 | (nz << 16);
+                ci.push_back(w);
+            }
+    }
+    c->ncitems = (int)ci.size();
+    HIP_TRY(c, hipMalloc(&c->d_citems, sizeof(WorkItem) * std::max<size_t>(1, ci.size())));
+    if (!ci.empty())
+        HIP_TRY(c, hipMemcpy(c->d_citems, ci.data(), sizeof(WorkItem) * ci.size(), hipMemcpyHostToDevice));
+    // inverse links: for block b, every (block X, dir, side, kind) whose guards copy cells of b
+    std::vector<std::vector<int4>> inc(c->nblocks);
+    for (int x = 0; x < c->nblocks; ++x)
+        for (int d = 0; d < nd; ++d)
+            for (int side = 0; side < 2; ++side) {
+                const int nb = c->hl[x].nbr[2 * d + side];
+                if (nb >= 0) inc[nb].push_back(make_int4(x, d, side, 0));
+                else if (nb == HYDRO_PERIODIC_SELF) inc[x].push_back(make_int4(x, d, side, 0));
+                else inc[x].push_back(make_int4(x, d, side, 1));
+            }
+    std::vector<int> start(c->nblocks + 1, 0);
+    std::vector<int4> flat;
+    for (int b = 0; b < c->nblocks; ++b) {
+        start[b] = (int)flat.size();
+        flat.insert(flat.end(), inc[b].begin(), inc[b].end());
+    }
+    start[c->nblocks] = (int)flat.size();
+    HIP_TRY(c, hipMalloc(&c->d_inc_start, sizeof(int) * start.size()));
+    HIP_TRY(c, hipMemcpy(c->d_inc_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMalloc(&c->d_inc, sizeof(int4) * std::max<size_t>(1, flat.size())));
+    if (!flat.empty())
+        HIP_TRY(c, hipMemcpy(c->d_inc, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice));
+    const size_t per = (size_t)c->nv * (size_t)std::max<int64_t>(1, c->ncell);
+    if (hipMalloc(&c->d_vjp, sizeof(double) * per * 3) != hipSuccess) {
+        c->d_vjp = nullptr;
+        return fail(c, HYDRO_ENOMEM, "adjoint scratch");
+    }
+    return HYDRO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -521,7 +601,65 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
 int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const double *gUnext, double *gUn)
 {
     if (!c || !Un || !dt_dev || !gUnext || !gUn) return fail(c, HYDRO_EINVAL, "null pointer");
-    return fail(c, HYDRO_EINVAL, "adjoint not available in this build");
+    if (gUn == gUnext) return fail(c, HYDRO_EINVAL, "gUn aliases gUnext");
+    if (c->nitems == 0) return HYDRO_OK;
+    int rc = setup_vjp(c);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    const int S = c->prm.rk, nd = c->prm.ndim;
+    const size_t per = (size_t)c->nv * (size_t)c->ncell;
+    // forward recomputation of the stage inputs U_2 .. U_S
+    const double *Us_of[4] = {nullptr, Un, c->d_buf[0], c->d_buf[1]};
+    for (int s = 1; s < S; ++s) {
+        StageArgs a = stage_args(c, s, dt_dev, Un, Us_of[s], c->d_buf[s - 1]);
+        hipError_t e = launch_stage(a, nd, c->prm.recon, c->tune.tile, true, persistent_grid(c), st);
+        if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+    }
+    HIP_TRY(c, hipMemsetAsync(gUn, 0, sizeof(double) * per, st));
+    double *gW = c->d_vjp, *gbuf[2] = {c->d_vjp + per, c->d_vjp + 2 * per};
+    const double *g = gUnext;
+    for (int s = S, q = 0; s >= 1; --s, q ^= 1) {
+        VjpArgs v{};
+        v.blocks = c->d_blocks;
+        v.faces = c->d_faces;
+        v.citems = c->d_citems;
+        v.ncitems = c->ncitems;
+        v.nc = c->ncell;
+        v.gamma = c->prm.gamma;
+        v.g1 = c->prm.gamma - 1.0;
+        v.ig1 = 1.0 / (c->prm.gamma - 1.0);
+        v.idx = 1.0 / c->prm.dx;
+        v.idy = 1.0 / c->prm.dy;
+        v.idz = 1.0 / c->prm.dz;
+        rk_coeffs(S, s, v.a, v.b);
+        v.dt = dt_dev;
+        v.Us = Us_of[s];
+        v.gOut = g;
+        v.gW = gW;
+        v.gUs = gbuf[q];
+        v.gUn = (s >= 2) ? gUn : nullptr;
+        v.inc_start = c->d_inc_start;
+        v.inc = c->d_inc;
+        for (int d = 0; d < nd; ++d) {
+            v.items = c->d_lines[d];
+            v.nitems = c->nlines[d];
+            hipError_t e = launch_vjp_lines(v, nd, c->prm.recon, d, c->nlines[d], st);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint line launch");
+        }
+        hipError_t e = launch_vjp_cells(v, nd, c->prm.recon, c->ncitems, st);
+        if (e != hipSuccess) return hip_fail(c, e, "adjoint cell launch");
+        g = gbuf[q];
+    }
+    VjpArgs v{};
+    v.blocks = c->d_blocks;
+    v.citems = c->d_citems;
+    v.ncitems = c->ncitems;
+    v.nc = c->ncell;
+    v.gUs = const_cast<double *>(g);
+    v.gUn = gUn;
+    hipError_t e = launch_vjp_add(v, nd, c->ncitems, st);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint add launch");
+    return HYDRO_OK;
 }
 
 int hydro_status(hydro_ctx_t *c, int64_t *n_nonphys)
@@ -557,6 +695,10 @@ void hydro_destroy(hydro_ctx_t *c)
     (void)hipFree(c->d_partial);
     (void)hipFree(c->d_nbad);
     (void)hipFree(c->d_vjp);
+    for (int d = 0; d < 3; ++d) (void)hipFree(c->d_lines[d]);
+    (void)hipFree(c->d_citems);
+    (void)hipFree(c->d_inc_start);
+    (void)hipFree(c->d_inc);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
 }

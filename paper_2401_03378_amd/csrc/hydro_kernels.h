@@ -43,25 +43,29 @@ struct GuardArgs {
 struct VjpArgs {
     const DevBlock *blocks;
     const FaceSrc *faces;
-    const WorkItem *items;
+    const WorkItem *items;      // line work items: block, first line (xy), line count (z)
     int32_t nitems;
-    int32_t stage;
+    const WorkItem *citems;     // cell work items (8x8 tiles over z)
+    int32_t ncitems;
     int64_t nc;
     double gamma, g1, ig1;
     double idx, idy, idz;
     double a, b;
     const double *dt;
-    const double *Us;          // stage input (forward state)
-    const double *gOut;        // cotangent of the stage output
-    double *gUs;               // cotangent of the stage input (interior), written
-    double *gUn;               // a_s gOut accumulated here (may be null for stage 1)
-    double *gHalo;             // per-item halo cotangent scratch
-    const int64_t *haloBase;   // per item: first slot in gHalo
-    unsigned long long *nbad;
+    const double *Us;           // stage input (forward state)
+    const double *gOut;         // cotangent of the stage output (interior)
+    double *gW;                 // padded primitive cotangents, nvar x nc
+    double *gUs;                // cotangent of the stage input (interior)
+    double *gUn;                // += a gOut (null: skip)
+    const int *inc_start;       // per block: range in inc
+    const int4 *inc;            // guard positions copying this block: (block, dir, side, kind)
 };
 
 hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, bool gather, int grid, hipStream_t st);
 hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl, double *dt, hipStream_t st);
 hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st);
+hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st);
+hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st);
+hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st);
 
 }  // namespace hydro

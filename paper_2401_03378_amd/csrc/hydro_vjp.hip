@@ -1,0 +1,588 @@
+// Adjoint (vector-Jacobian product) of one SSP-RK stage on gfx950, with the
+// time step held fixed and every branch (limiter slope, positivity fallback,
+// HLLC region, Davis min/max argument) taken as the forward step takes it at
+// the same state.
+//
+// A stage is U_{s+1} = b (U_s + dt L(U_s)) + a U^n with
+// L = -sum_d (F_{d,i+1/2} - F_{d,i-1/2})/dx_d.  Its transpose splits into
+//  k_vjp_lines<D>  one thread per 1D line of a block along direction D,
+//                  streaming along the line: it recomputes primitives,
+//                  reconstruction (with fallback) and the HLLC branch, then
+//                  reverses face flux -> face states -> stencil primitives,
+//                  and writes the primitive cotangent gW of every position the
+//                  line's stencils read (interior and guard positions) into a
+//                  padded array.  Directions run as successive launches, so
+//                  interior sums are race-free and in a fixed order.
+//  k_vjp_cells     one thread per interior cell: adds the cotangents of the
+//                  guard positions that are copies of the cell (through the
+//                  inverse link table; neighbour, periodic and outflow
+//                  copies), applies the EOS transpose and forms
+//                  gU_s = b gOut + (dW/dU)^T gW, gU^n += a gOut.
+// The guard-fill transpose is thus a deterministic gather, not an atomic
+// scatter.
+#include "hydro_kernels.h"
+
+namespace hydro {
+
+// ------------------------------------------------------- point-wise VJPs
+
+template <int NDIM, int N>
+__device__ __forceinline__ void state_flux_vjp(const double (&w)[5], const double (&gU)[5], const double (&gF)[5],
+                                               double gc, double gr, double (&gW)[5], const Consts &K)
+{
+    constexpr int NV = NDIM + 2;
+    const double rho = w[0], p = w[4], un = w[1 + N];
+    double u2;
+    if constexpr (NDIM == 3)
+        u2 = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
+    else
+        u2 = w[1] * w[1] + w[2] * w[2];
+    const double E = p * K.ig1 + 0.5 * (rho * u2);
+    const double fr = rho * un;
+    double grho = 0.0, gp = 0.0, gE = 0.0, gu[3] = {0.0, 0.0, 0.0};
+    double gfr = gF[0];
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        gfr += gF[1 + d] * w[1 + d];
+        gu[d] += gF[1 + d] * fr;
+    }
+    gp += gF[1 + N];
+    gE += gF[NV - 1] * un;
+    gp += gF[NV - 1] * un;
+    gu[N] += gF[NV - 1] * (E + p);
+    grho += gfr * un;
+    gu[N] += gfr * rho;
+    grho += gU[0];
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        grho += gU[1 + d] * w[1 + d];
+        gu[d] += gU[1 + d] * rho;
+    }
+    gE += gU[NV - 1];
+    gp += gE * K.ig1;
+    grho += gE * 0.5 * u2;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) gu[d] += gE * rho * w[1 + d];
+    const double r = 1.0 / rho, c = sqrt((K.gamma * p) * r);
+    const double gx = gc / (2.0 * c);
+    gp += gx * K.gamma * r;
+    const double grt = gr + gx * K.gamma * p;
+    grho += -r * r * grt;
+    gW[0] += grho;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) gW[1 + d] += gu[d];
+    gW[4] += gp;
+}
+
+// Reverse of the HLLC flux: recomputes the forward face solution (region and
+// Davis arguments included) and accumulates gWL, gWR.
+template <int NDIM, int N>
+__device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&WR)[5], const double (&gF)[5],
+                                         double (&gWL)[5], double (&gWR)[5], const Consts &K)
+{
+    constexpr int NV = NDIM + 2;
+    double UL[5], UR[5], FL[5], FR[5], rL, rR, cL, cR;
+    state_flux<NDIM, N>(WL, UL, FL, rL, cL, K);
+    state_flux<NDIM, N>(WR, UR, FR, rR, cR, K);
+    const double uL = WL[1 + N], uR = WR[1 + N];
+    const double sl0 = uL - cL, sl1 = uR - cR, sr0 = uL + cL, sr1 = uR + cR;
+    const bool slR = !(sl0 <= sl1);   // S_L from the right state
+    const bool srR = !(sr0 >= sr1);   // S_R from the right state
+    const double SL = slR ? sl1 : sl0, SR = srR ? sr1 : sr0;
+    const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
+    const double Num = (WR[4] - WL[4]) + (mL * uL - mR * uR), Den = mL - mR;
+    const double Ss = Num / Den;
+    double gUL[5] = {0, 0, 0, 0, 0}, gUR[5] = {0, 0, 0, 0, 0}, gFL[5] = {0, 0, 0, 0, 0}, gFR[5] = {0, 0, 0, 0, 0};
+    double gcL = 0.0, gcR = 0.0, grL = 0.0, grR = 0.0;
+    if (SL >= 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gFL[v] = gF[v];
+    } else if (Ss >= 0.0 || SR > 0.0) {
+        const bool right = !(Ss >= 0.0);
+        const double(&W)[5] = right ? WR : WL;
+        const double(&UK)[5] = right ? UR : UL;
+        const double SK = right ? SR : SL, mK = right ? mR : mL, rK = right ? rR : rL;
+        const double uK = W[1 + N];
+        const double den = SK - Ss, chi = mK / den;
+        const double q = W[4] / mK;
+        const double Bq = UK[NV - 1] * rK + (Ss - uK) * (Ss + q);
+        double Us[5];
+        Us[0] = chi;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) Us[1 + d] = (d == N) ? chi * Ss : chi * W[1 + d];
+        Us[NV - 1] = chi * Bq;
+        double gSK = 0.0, gUs[5], gUK[5];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            gSK += gF[v] * (Us[v] - UK[v]);
+            gUs[v] = SK * gF[v];
+            gUK[v] = -(SK * gF[v]);
+        }
+        double gWK[5] = {0, 0, 0, 0, 0};
+        double gchi = gUs[0] + gUs[1 + N] * Ss + gUs[NV - 1] * Bq;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d)
+            if (d != N) {
+                gchi += gUs[1 + d] * W[1 + d];
+                gWK[1 + d] += gUs[1 + d] * chi;
+            }
+        double gSs = gUs[1 + N] * chi;
+        const double gB = gUs[NV - 1] * chi;
+        gUK[NV - 1] += gB * rK;
+        const double grK = gB * UK[NV - 1];
+        gSs += gB * (Ss + q) + gB * (Ss - uK);
+        gWK[1 + N] -= gB * (Ss + q);
+        const double gq = gB * (Ss - uK);
+        gWK[4] += gq / mK;
+        double gmK = -gq * q / mK;
+        gmK += gchi / den;
+        const double gden = -gchi * chi / den;
+        gSK += gden;
+        gSs -= gden;
+        double gSL = 0.0, gSR = 0.0, gmL = 0.0, gmR = 0.0;
+        if (right) {
+            gSR += gSK; gmR += gmK; grR += grK;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) { gFR[v] = gF[v]; gUR[v] = gUK[v]; }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gWR[v] += gWK[v];
+        } else {
+            gSL += gSK; gmL += gmK; grL += grK;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) { gFL[v] = gF[v]; gUL[v] = gUK[v]; }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gWL[v] += gWK[v];
+        }
+        const double gN = gSs / Den, gD = -gSs * Ss / Den;
+        gWR[4] += gN;
+        gWL[4] -= gN;
+        gmL += gN * uL + gD;
+        gmR += -gN * uR - gD;
+        double guL = gN * mL, guR = -gN * mR;
+        gWL[0] += gmL * (SL - uL);
+        gSL += gmL * WL[0];
+        guL -= gmL * WL[0];
+        gWR[0] += gmR * (SR - uR);
+        gSR += gmR * WR[0];
+        guR -= gmR * WR[0];
+        if (slR) { guR += gSL; gcR -= gSL; } else { guL += gSL; gcL -= gSL; }
+        if (srR) { guR += gSR; gcR += gSR; } else { guL += gSR; gcL += gSR; }
+        gWL[1 + N] += guL;
+        gWR[1 + N] += guR;
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gFR[v] = gF[v];
+    }
+    state_flux_vjp<NDIM, N>(WL, gUL, gFL, gcL, grL, gWL, K);
+    state_flux_vjp<NDIM, N>(WR, gUR, gFR, gcR, grR, gWR, K);
+}
+
+// Reverse of the limited linear slope of (qa, q0, qb): adds to g[0..2].
+__device__ __forceinline__ void plm_vjp(double qa, double q0, double qb, double gqm, double gqp, double *g)
+{
+    const double dm = q0 - qa, dp = qb - q0;
+    const double gs = 0.5 * gqp - 0.5 * gqm;
+    double gdm = 0.0, gdp = 0.0;
+    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
+        const double a = 0.5 * (dm + dp);
+        const double aa = fabs(a), m2 = 2.0 * fabs(dm), p2 = 2.0 * fabs(dp);
+        const double side = dmin(m2, p2);
+        if (aa <= side) { gdm = 0.5 * gs; gdp = 0.5 * gs; }
+        else if (m2 <= p2) gdm = 2.0 * gs;
+        else gdp = 2.0 * gs;
+    }
+    g[0] -= gdm;
+    g[1] += gqm + gqp + gdm - gdp;
+    g[2] += gdp;
+}
+
+// Reverse of WENO5-JS on (a,b,c,d,e): adds to g[0..4].
+__device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gqp, double *g)
+{
+    const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
+    const double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
+    double t[3], w[3], be[3], o[3];
+    t[0] = (a - 2.0 * b) + c;
+    w[0] = (a - 4.0 * b) + 3.0 * c;
+    t[1] = (b - 2.0 * c) + d;
+    w[1] = b - d;
+    t[2] = (c - 2.0 * d) + e;
+    w[2] = (3.0 * c - 4.0 * d) + e;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        be[k] = k13 * (t[k] * t[k]) + 0.25 * (w[k] * w[k]);
+        o[k] = 1.0 / ((eps + be[k]) * (eps + be[k]));
+    }
+    double go0 = 0.0, go1 = 0.0, go2 = 0.0;
+    {   // right face
+        const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * k6;
+        const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;
+        const double p2 = ((2.0 * c + 5.0 * d) - e) * k6;
+        const double a0 = 0.1 * o[0], a1 = 0.6 * o[1], a2 = 0.3 * o[2];
+        const double S = (a0 + a1) + a2;
+        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) / S;
+        const double gp0 = gqp * a0 / S, gp1 = gqp * a1 / S, gp2 = gqp * a2 / S;
+        go0 += 0.1 * gqp * (p0 - qv) / S;
+        go1 += 0.6 * gqp * (p1 - qv) / S;
+        go2 += 0.3 * gqp * (p2 - qv) / S;
+        g[0] += k6 * (2.0 * gp0);
+        g[1] += k6 * (-7.0 * gp0 - gp1);
+        g[2] += k6 * (11.0 * gp0 + 5.0 * gp1 + 2.0 * gp2);
+        g[3] += k6 * (2.0 * gp1 + 5.0 * gp2);
+        g[4] += k6 * (-gp2);
+    }
+    {   // left face: mirrored candidates, weights (0.1 o2, 0.6 o1, 0.3 o0)
+        const double p0 = ((2.0 * e - 7.0 * d) + 11.0 * c) * k6;
+        const double p1 = ((-d + 5.0 * c) + 2.0 * b) * k6;
+        const double p2 = ((2.0 * c + 5.0 * b) - a) * k6;
+        const double a0 = 0.1 * o[2], a1 = 0.6 * o[1], a2 = 0.3 * o[0];
+        const double S = (a0 + a1) + a2;
+        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) / S;
+        const double gp0 = gqm * a0 / S, gp1 = gqm * a1 / S, gp2 = gqm * a2 / S;
+        go2 += 0.1 * gqm * (p0 - qv) / S;
+        go1 += 0.6 * gqm * (p1 - qv) / S;
+        go0 += 0.3 * gqm * (p2 - qv) / S;
+        g[4] += k6 * (2.0 * gp0);
+        g[3] += k6 * (-7.0 * gp0 - gp1);
+        g[2] += k6 * (11.0 * gp0 + 5.0 * gp1 + 2.0 * gp2);
+        g[1] += k6 * (2.0 * gp1 + 5.0 * gp2);
+        g[0] += k6 * (-gp2);
+    }
+    const double go[3] = {go0, go1, go2};
+    double gt[3], gw[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double gbe = -2.0 * go[k] * o[k] / (eps + be[k]);
+        gt[k] = 2.0 * k13 * t[k] * gbe;
+        gw[k] = 0.5 * w[k] * gbe;
+    }
+    g[0] += gt[0] + gw[0];
+    g[1] += -2.0 * gt[0] - 4.0 * gw[0] + gt[1] + gw[1];
+    g[2] += gt[0] + 3.0 * gw[0] - 2.0 * gt[1] + gt[2] + 3.0 * gw[2];
+    g[3] += gt[1] - gw[1] - 2.0 * gt[2] - 4.0 * gw[2];
+    g[4] += gt[2] + gw[2];
+}
+
+// Reverse of one cell's reconstruction along a line: s[c][v] stencil
+// (2R+1 cells); fb: the positivity fallback fired (faces = cell value).
+template <int NDIM, int RECON, int S>
+__device__ __forceinline__ void recon_cell_vjp(const double (&s)[S][5], bool fb, const double (&gqm)[5],
+                                               const double (&gqp)[5], double (&g)[S][5])
+{
+    constexpr int R = (RECON == kWENO) ? 2 : 1;
+    if (fb) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) g[R][v] += gqm[v] + gqp[v];
+        return;
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (NDIM == 2 && v == 3) continue;
+        double st[2 * R + 1], gs[2 * R + 1];
+#pragma unroll
+        for (int k = 0; k < 2 * R + 1; ++k) { st[k] = s[k][v]; gs[k] = 0.0; }
+        if constexpr (RECON == kWENO)
+            weno5_vjp(st, gqm[v], gqp[v], gs);
+        else
+            plm_vjp(st[0], st[1], st[2], gqm[v], gqp[v], gs);
+#pragma unroll
+        for (int k = 0; k < 2 * R + 1; ++k) g[k][v] += gs[k];
+    }
+}
+
+// primitive slot of the padded cotangent array: rho, u_1..u_nd, p
+template <int NDIM>
+__device__ __forceinline__ int wslot(int v) { return v == 4 ? NDIM + 1 : v; }
+
+// ------------------------------------------------------------ line kernel
+
+template <int D>
+__device__ __forceinline__ void line_coords(int t, int e1, int e2, int &i, int &j, int &k)
+{
+    if (D == 0) { i = t; j = e1; k = e2; }
+    else if (D == 1) { i = e1; j = t; k = e2; }
+    else { i = e1; j = e2; k = t; }
+}
+
+template <int NDIM, int RECON, int D>
+__global__ void __launch_bounds__(64) k_vjp_lines(VjpArgs A)
+{
+    constexpr int R = (RECON == kWENO) ? 2 : 1;
+    constexpr int H = R + 1;
+    constexpr int NV = NDIM + 2;
+    constexpr int NS = 2 * R + 1;     // stencil
+    constexpr int NWIN = 2 * R + 2;   // primitives at positions t-2R-1 .. t
+    const WorkItem it = A.items[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int nl = it.z;               // lines in this item
+    if (lane >= nl) return;
+    const DevBlock B = A.blocks[it.block];
+    const FaceSrc *F6 = A.faces + 6 * (int64_t)it.block;
+    const int L = it.xy + lane;
+    const int n1 = (D == 0) ? B.ny : B.nx;
+    const int e1 = L % n1, e2 = L / n1;
+    const int n = (D == 0) ? B.nx : ((D == 1) ? B.ny : B.nz);
+    const int64_t nc = A.nc;
+    const Consts K{A.gamma, A.g1, A.ig1};
+    const double dt = *A.dt;
+    const double id = (D == 0) ? A.idx : ((D == 1) ? A.idy : A.idz);
+
+    double Wwin[NWIN][5];
+    double gWwin[NS][5];
+    double qp_prev[5], gqm_prev[5], gD_prev[5];
+    bool fb_prev = false;
+#pragma unroll
+    for (int c = 0; c < NWIN; ++c)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Wwin[c][v] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NS; ++c)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gWwin[c][v] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { qp_prev[v] = 0.0; gqm_prev[v] = 0.0; gD_prev[v] = 0.0; }
+
+    auto emit = [&](int p, const double (&gw)[5]) {
+        int i, j, k;
+        line_coords<D>(p, e1, e2, i, j, k);
+        const int64_t ci = cell_at(B, i, j, k);
+        const bool inner = (p >= 0 && p < n);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            if (NDIM == 2 && v == 3) continue;
+            double *dst = A.gW + (int64_t)wslot<NDIM>(v) * nc + ci;
+            if (D == 0 || !inner) *dst = gw[v];
+            else *dst = *dst + gw[v];
+        }
+    };
+
+    for (int t = -H; t < n + H; ++t) {
+        // primitives at the new position
+#pragma unroll
+        for (int c = 0; c < NWIN - 1; ++c)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Wwin[c][v] = Wwin[c + 1][v];
+        {
+            int i, j, k;
+            line_coords<D>(t, e1, e2, i, j, k);
+            double u[5];
+            load_cons<NDIM>(A.Us, nc, src_cell<D, true>(B, F6, i, j, k), u);
+            eos<NDIM>(u, Wwin[NWIN - 1], K.g1);
+        }
+        const int c = t - R;          // reconstruction cell completed by this position
+        if (c >= -1) {
+            double s[NS][5], qm[5], qp[5];
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) s[q][v] = Wwin[q + 1][v];
+            const bool fb = recon_cell<NDIM, RECON>(s, qm, qp);
+            double gqp_c1[5] = {0, 0, 0, 0, 0}, gqm_c[5] = {0, 0, 0, 0, 0};
+            if (c >= 0) {
+                // cotangent of face c-1/2: gD_{c-1} - gD_c
+                double gD[5] = {0, 0, 0, 0, 0};
+                if (c < n) {
+                    int i, j, k;
+                    line_coords<D>(c, e1, e2, i, j, k);
+                    const int64_t ci = cell_at(B, i, j, k);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const double gT = A.b * A.gOut[v * nc + ci];
+                        gD[v] = -(dt * gT) * id;
+                    }
+                }
+                double gF[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+                for (int v = 0; v < NV; ++v) gF[v] = gD_prev[v] - gD[v];
+                hllc_vjp<NDIM, D>(qp_prev, qm, gF, gqp_c1, gqm_c, K);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) gD_prev[v] = gD[v];
+                // cell c-1 now has both face cotangents
+                double s1[NS][5], g1[NS][5];
+#pragma unroll
+                for (int q = 0; q < NS; ++q)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) { s1[q][v] = Wwin[q][v]; g1[q][v] = 0.0; }
+                recon_cell_vjp<NDIM, RECON>(s1, fb_prev, gqm_prev, gqp_c1, g1);
+#pragma unroll
+                for (int q = 0; q < NS; ++q)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) gWwin[q][v] += g1[q][v];
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) { qp_prev[v] = qp[v]; gqm_prev[v] = gqm_c[v]; }
+            fb_prev = fb;
+        }
+        // position t-2R-1 receives nothing more
+        const int pout = t - 2 * R - 1;
+        if (pout >= -H) emit(pout, gWwin[0]);
+#pragma unroll
+        for (int q = 0; q < NS - 1; ++q)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gWwin[q][v] = gWwin[q + 1][v];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gWwin[NS - 1][v] = 0.0;
+    }
+    // last reconstruction cell (n): no face on its right in this block
+    {
+        double s1[NS][5], g1[NS][5];
+        const double zero[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) { s1[q][v] = Wwin[q + 1][v]; g1[q][v] = 0.0; }
+        recon_cell_vjp<NDIM, RECON>(s1, fb_prev, gqm_prev, zero, g1);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gWwin[q][v] += g1[q][v];
+            emit(n - R + q, gWwin[q]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ cell kernel
+
+// Reverse of the EOS at one cell: gU (nvar) = (dW/dU)^T gW.
+template <int NDIM>
+__device__ __forceinline__ void eos_vjp(const double (&u)[5], const double (&gw)[5], double (&gu)[5], double g1)
+{
+    const double r = 1.0 / u[0];
+    const double gke = -g1 * gw[4];
+    double gr = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gu[v] = 0.0;
+    gu[NDIM + 1] = g1 * gw[4];
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        const double ud = u[1 + d] * r;
+        const double g = gw[1 + d] + 0.5 * u[1 + d] * gke;
+        gu[1 + d] = 0.5 * ud * gke + r * g;
+        gr += u[1 + d] * g;
+    }
+    gu[0] = gw[0] - r * r * gr;
+}
+
+template <int NDIM, int H, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
+{
+    constexpr int NV = NDIM + 2;
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const int64_t nc = A.nc;
+    for (int w = blockIdx.x; w < A.ncitems; w += gridDim.x) {
+        const WorkItem it = A.citems[w];
+        const DevBlock B = A.blocks[it.block];
+        const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
+        const int z0 = it.z & 0xffff, nzc = it.z >> 16;
+        const int i = x0 + tx, j = y0 + ty;
+        if (i >= B.nx || j >= B.ny) continue;
+        const int inc0 = A.inc_start[it.block], inc1 = A.inc_start[it.block + 1];
+        for (int k = z0; k < z0 + nzc; ++k) {
+            const int64_t ci = cell_at(B, i, j, k);
+            double gw[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gw[v] = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] = A.gW[v * nc + ci];
+            // guard positions (of this or other blocks) that copy this cell
+            for (int e = inc0; e < inc1; ++e) {
+                const int4 q = A.inc[e];                 // x = block, y = dir, z = side, w = kind
+                const DevBlock X = A.blocks[q.x];
+                const int d = q.y;
+                const int pos = (d == 0) ? i : ((d == 1) ? j : k);
+                const int nb = (d == 0) ? B.nx : ((d == 1) ? B.ny : B.nz);
+                const int nx_ = (d == 0) ? X.nx : ((d == 1) ? X.ny : X.nz);
+                int lo = 1, hi = 0, gp0 = 0, step = 0;
+                if (q.w == 0) {                          // copy: layer l <-> one position
+                    if (q.z == 0) { const int l = nb - pos; if (l >= 1 && l <= H) { lo = hi = l; } gp0 = 0; step = -1; }
+                    else { const int l = pos + 1; if (l <= H) { lo = hi = l; } gp0 = nx_ - 1; step = 1; }
+                } else {                                 // outflow: every layer copies the boundary cell
+                    if (q.z == 0 && pos == 0) { lo = 1; hi = H; gp0 = 0; step = -1; }
+                    if (q.z == 1 && pos == nb - 1) { lo = 1; hi = H; gp0 = nx_ - 1; step = 1; }
+                }
+                for (int l = lo; l <= hi; ++l) {
+                    const int gpos = gp0 + step * l;
+                    const int gi = (d == 0) ? gpos : i, gj = (d == 1) ? gpos : j, gk = (d == 2) ? gpos : k;
+                    const int64_t gc = cell_at(X, gi, gj, gk);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] += A.gW[v * nc + gc];
+                }
+            }
+            double u[5], gu[5];
+            load_cons<NDIM>(A.Us, nc, ci, u);
+            eos_vjp<NDIM>(u, gw, gu, A.g1);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double go = A.gOut[v * nc + ci];
+                A.gUs[v * nc + ci] = A.b * go + gu[v];
+                if (A.gUn) A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + A.a * go;
+            }
+        }
+    }
+}
+
+// Final accumulation gUn += g (cotangent of the first stage's input U^n).
+template <int NDIM, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) k_vjp_add(VjpArgs A)
+{
+    constexpr int NV = NDIM + 2;
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const int64_t nc = A.nc;
+    for (int w = blockIdx.x; w < A.ncitems; w += gridDim.x) {
+        const WorkItem it = A.citems[w];
+        const DevBlock B = A.blocks[it.block];
+        const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
+        const int z0 = it.z & 0xffff, nzc = it.z >> 16;
+        const int i = x0 + tx, j = y0 + ty;
+        if (i >= B.nx || j >= B.ny) continue;
+        for (int k = z0; k < z0 + nzc; ++k) {
+            const int64_t ci = cell_at(B, i, j, k);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + A.gUs[v * nc + ci];
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+template <int NDIM, int RECON>
+static hipError_t launch_vjp_lines_r(const VjpArgs &a, int d, int nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (d == 0) k_vjp_lines<NDIM, RECON, 0><<<nitems, 64, 0, st>>>(a);
+    else if (d == 1) k_vjp_lines<NDIM, RECON, 1><<<nitems, 64, 0, st>>>(a);
+    else if constexpr (NDIM == 3) k_vjp_lines<NDIM, RECON, 2><<<nitems, 64, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st)
+{
+    if (ndim == 3)
+        return recon == kWENO ? launch_vjp_lines_r<3, kWENO>(a, d, nitems, st)
+                              : launch_vjp_lines_r<3, kPLM>(a, d, nitems, st);
+    return recon == kWENO ? launch_vjp_lines_r<2, kWENO>(a, d, nitems, st)
+                          : launch_vjp_lines_r<2, kPLM>(a, d, nitems, st);
+}
+
+hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    if (ndim == 3) {
+        if (recon == kWENO) k_vjp_cells<3, 3, 8, 8><<<grid, 64, 0, st>>>(a);
+        else k_vjp_cells<3, 2, 8, 8><<<grid, 64, 0, st>>>(a);
+    } else {
+        if (recon == kWENO) k_vjp_cells<2, 3, 8, 8><<<grid, 64, 0, st>>>(a);
+        else k_vjp_cells<2, 2, 8, 8><<<grid, 64, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    if (ndim == 3) k_vjp_add<3, 8, 8><<<grid, 64, 0, st>>>(a);
+    else k_vjp_add<2, 8, 8><<<grid, 64, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace hydro
