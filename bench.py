@@ -63,6 +63,46 @@ def cpu_baseline(prob, budget_s):
             "sample": f"first {steps} step(s) of the same workload ({zs} zone-stages, {el:.1f} s)"}
 
 
+def extras(S, prob, U0, ms_per_step):
+    """Adjoint/forward cost of a checkpointed rollout (the config's 20 steps,
+    checkpoint every 5, dt frozen) and the plain per-block-launch form of the
+    same step, both on this GPU."""
+    import torch
+    from paper_2401_03378_amd.adjoint import rollout, rollout_vjp, TorchStepper
+    st = TorchStepper(S)
+    n, k = prob.nsteps, 5
+    UN, tape = rollout(st, U0, 2, 1)                 # warm-up: graph, adjoint scratch
+    rollout_vjp(st, tape, torch.nan_to_num(UN))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    UN, tape = rollout(st, U0, n, n + 1)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    UN, tape = rollout(st, U0, n, k)
+    rollout_vjp(st, tape, torch.nan_to_num(UN))
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    S.status()
+    tuned = S.tuning()
+    S.set_tuning(mode=1, use_graph=0)
+    U = U0.clone()
+    S.step(U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        S.step(U)
+    torch.cuda.synchronize()
+    tpb = (time.perf_counter() - t0) / 2
+    S.status()
+    S.set_tuning(**tuned)
+    return {"adjoint_over_forward": round(tb / tf, 3),
+            "adjoint_detail": f"{n}-step rollout, checkpoint every {k}: forward {tf * 1e3:.2f} ms, "
+                              f"forward + checkpointed backward {tb * 1e3:.2f} ms",
+            "perblock_ms_per_step": round(tpb * 1e3, 3),
+            "speedup_vs_perblock": round(tpb * 1e3 / ms_per_step, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +112,8 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=10, help="steps timed per stage launch with events")
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 512 MiB device copy")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint/forward and per-block-launch comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -167,6 +209,8 @@ def main():
         "roofline": roof,
         "hbm_effective_frac": round(hbm_frac, 4),
     }
+    if not args.no_extras:
+        out.update(extras(S, prob, U0, ms_per_step))
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(W.config(1), args.cpu_budget)
     S.close()
