@@ -84,6 +84,7 @@ typedef struct {
 /* Launch configuration of the stage kernels (chosen by an autotuner). */
 #define HYDRO_MODE_PERSISTENT 0  /* one launch per stage over all blocks */
 #define HYDRO_MODE_PERBLOCK 1    /* per block: guard-fill launch + stage launch */
+#define HYDRO_MODE_TELESCOPING 2 /* one thick guard fill per step, stages on the extended blocks */
 typedef struct {
     int32_t mode;       /* HYDRO_MODE_* */
     int32_t tile;       /* xy tile of a work item: 0 = 8x8, 1 = 16x8, 2 = 16x16 */
@@ -111,7 +112,15 @@ int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks,
                  const hydro_link_t *links, int32_t nblocks, int64_t ncell_total,
                  void *stream, hydro_ctx_t **out);
 
-/* Replace / read the launch configuration.  Invalidates captured graphs. */
+/* Replace / read the launch configuration.  Invalidates captured graphs.
+ * HYDRO_MODE_TELESCOPING is the paper's telescoping RK variant (Sec. 4.2,
+ * second RK listing): per step one guard fill into thick block copies with
+ * S*(R+1) layers (R = 1 PLM, 2 WENO5; edges and corners included), then all
+ * stages update the blocks together with the halo later stages read.  It
+ * equals the per-stage-fill step bit for bit on domains without outflow
+ * faces and differs at outflow faces.  It needs every neighbour / periodic
+ * source block to be at least S*(R+1) cells deep (else HYDRO_EINVAL); in it,
+ * hydro_rk_stage and hydro_step_vjp return HYDRO_EINVAL. */
 int hydro_set_tuning(hydro_ctx_t *ctx, const hydro_tuning_t *tuning);
 int hydro_get_tuning(hydro_ctx_t *ctx, hydro_tuning_t *tuning);
 

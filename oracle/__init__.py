@@ -65,6 +65,7 @@ def lib():
             "ora_rk_stage": (C.c_int, [P, C.c_int, C.c_double, dp, dp, dp]),
             "ora_step": (C.c_int, [P, dp, dp, C.c_int]),
             "ora_step_vjp": (C.c_int, [P, dp, C.c_double, dp, dp]),
+            "ora_step_telescoping": (C.c_int, [P, dp, dp, C.c_int]),
             "ora_cs_step": (C.c_int, [P, dp, dp, C.c_double]),
             "ora_eos_n": (C.c_int, [P, i64, dp, dp]),
             "ora_plm_n": (None, [i64, dp, dp, dp, ip]),
@@ -161,6 +162,15 @@ def step(prob, U, dt=None) -> float:
     P = _as_problem(prob)
     d = np.array([0.0 if dt is None else float(dt)])
     _check(lib().ora_step(P.ptr, _dp(U), _dp(d), 1 if dt is None else 0), "step")
+    return float(d[0])
+
+
+def step_telescoping(prob, U, dt=None) -> float:
+    """One telescoping step in place (one thick guard fill per step, stages
+    updated on the shrinking extended region); returns the dt used."""
+    P = _as_problem(prob)
+    d = np.array([0.0 if dt is None else float(dt)])
+    _check(lib().ora_step_telescoping(P.ptr, _dp(U), _dp(d), 1 if dt is None else 0), "step_telescoping")
     return float(d[0])
 
 

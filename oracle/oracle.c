@@ -166,6 +166,145 @@ int ora_step(const ora_problem *P, double *U, double *dt, int compute_dt)
     return bad ? ORA_ENONPHYS : ORA_OK;
 }
 
+/* ------------------------------------------------------ telescoping step */
+
+/* Telescoping variant of the SSP-RK step (the paper's second RK listing in
+ * Sec. 4.2): the guard cells are filled once per step, with a halo thick
+ * enough for all stages (S*(R+1) layers, edges and corners included), and
+ * every stage then updates the block together with the part of its halo
+ * that later stages still read, instead of refilling guards between stages.
+ *
+ * Thick copies of the blocks live in a separate buffer.  The halo is filled
+ * one direction after the other: direction d fills its layers over the
+ * already-filled extents of the directions before it, which fills edges and
+ * corners from the neighbours of neighbours (or by wrap / nearest-cell copy).
+ * Stage s then runs on "virtual" blocks that are the interior extended by
+ * m = (S - s)(R + 1) cells on every side. */
+
+static int tele_width(const ora_problem *P) { return P->rk * ((P->recon == 1) ? 3 : 2); }
+
+static void thick_table(const ora_problem *P, int ngt, ora_block *T, int64_t *ncell_t)
+{
+    int64_t off = 0;
+    for (int b = 0; b < P->nblocks; b++) {
+        const ora_block *B = &P->blocks[b];
+        T[b].nx = B->nx; T[b].ny = B->ny; T[b].nz = B->nz; T[b].ng = ngt; T[b].offset = off;
+        int64_t pz = (P->ndim == 3) ? B->nz + 2 * ngt : 1;
+        off += (int64_t)(B->nx + 2 * ngt) * (B->ny + 2 * ngt) * pz;
+    }
+    *ncell_t = off;
+}
+
+/* Copy the interior of U into the thick buffer and fill its halo. */
+static void thick_fill(const ora_problem *P, const ora_block *T, int64_t nct, const double *U, double *Ut)
+{
+    const int nd = P->ndim, nv = nd + 2;
+    for (int b = 0; b < P->nblocks; b++) {
+        const ora_block *B = &P->blocks[b];
+        for (int k = 0; k < B->nz; k++)
+            for (int j = 0; j < B->ny; j++)
+                for (int i = 0; i < B->nx; i++)
+                    for (int v = 0; v < nv; v++)
+                        Ut[v * nct + ora_r_cell(&T[b], nd, i, j, k)] = U[v * P->ncell + ora_r_cell(B, nd, i, j, k)];
+    }
+    for (int d = 0; d < nd; d++)
+        for (int b = 0; b < P->nblocks; b++) {
+            const ora_block *B = &T[b];
+            const int g = B->ng;
+            int lo[3], hi[3];        /* ranges of the other coordinates */
+            for (int e = 0; e < 3; e++) {
+                int n = ora_r_extent(B, e);
+                if (e >= nd) { lo[e] = 0; hi[e] = 1; }
+                else if (e < d) { lo[e] = -g; hi[e] = n + g; }
+                else { lo[e] = 0; hi[e] = n; }
+            }
+            int n = ora_r_extent(B, d);
+            for (int side = 0; side < 2; side++) {
+                int nb = P->links[b].nbr[2 * d + side];
+                for (int l = 1; l <= g; l++) {
+                    int gpos = (side == 0) ? -l : n - 1 + l;
+                    int sb = b, spos;
+                    if (nb >= 0) { sb = nb; spos = (side == 0) ? ora_r_extent(&T[nb], d) - l : l - 1; }
+                    else if (nb == -2) spos = (side == 0) ? n - l : l - 1;
+                    else spos = (side == 0) ? 0 : n - 1;
+                    lo[d] = 0; hi[d] = 1;
+                    for (int c2 = lo[2]; c2 < hi[2]; c2++)
+                        for (int c1 = lo[1]; c1 < hi[1]; c1++)
+                            for (int c0 = lo[0]; c0 < hi[0]; c0++) {
+                                int gc[3] = {c0, c1, c2}, sc[3] = {c0, c1, c2};
+                                gc[d] = gpos;
+                                sc[d] = spos;
+                                int64_t gi = ora_r_cell(B, nd, gc[0], gc[1], gc[2]);
+                                int64_t si = ora_r_cell(&T[sb], nd, sc[0], sc[1], sc[2]);
+                                for (int v = 0; v < nv; v++) Ut[v * nct + gi] = Ut[v * nct + si];
+                            }
+                }
+            }
+        }
+}
+
+/* One telescoping step in place on U. */
+int ora_step_telescoping(const ora_problem *P, double *U, double *dt, int compute_dt)
+{
+    int rc = validate(P);
+    if (rc) return rc;
+    const int H = (P->recon == 1) ? 3 : 2, S = P->rk, ngt = tele_width(P);
+    for (int b = 0; b < P->nblocks; b++)
+        for (int d = 0; d < P->ndim; d++) {
+            int nb = P->links[b].nbr[2 * d], nb2 = P->links[b].nbr[2 * d + 1];
+            if ((nb >= 0 && ora_r_extent(&P->blocks[nb], d) < ngt) ||
+                (nb2 >= 0 && ora_r_extent(&P->blocks[nb2], d) < ngt) ||
+                ((nb == -2 || nb2 == -2) && ora_r_extent(&P->blocks[b], d) < ngt))
+                return ORA_EINVAL;             /* halo deeper than the source block */
+        }
+    if (compute_dt) {
+        rc = ora_cfl_dt(P, U, dt);
+        if (rc) return rc;
+    }
+    if (!(*dt > 0.0)) return ORA_EINVAL;
+    const int nv = P->ndim + 2;
+    ora_block *T = malloc(sizeof(ora_block) * (size_t)(P->nblocks > 0 ? P->nblocks : 1));
+    ora_block *V = malloc(sizeof(ora_block) * (size_t)(P->nblocks > 0 ? P->nblocks : 1));
+    int64_t nct;
+    thick_table(P, ngt, T, &nct);
+    size_t bytes = sizeof(double) * (size_t)nv * (size_t)nct;
+    double *Un = malloc(bytes), *Ua = malloc(bytes), *Ub = malloc(bytes);
+    if (!T || !V || !Un || !Ua || !Ub) { free(T); free(V); free(Un); free(Ua); free(Ub); return ORA_ENOMEM; }
+    for (size_t q = 0; q < bytes / sizeof(double); q++) Un[q] = NAN;
+    thick_fill(P, T, nct, U, Un);
+    memcpy(Ua, Un, bytes);
+    memcpy(Ub, Un, bytes);
+    int64_t bad = 0;
+    const double *in = Un;
+    double *out = Ua;
+    for (int s = 1; s <= S; s++) {
+        const int m = (S - s) * H;          /* cells beyond the interior still needed */
+        for (int b = 0; b < P->nblocks; b++) {
+            const int mz = (P->ndim == 3) ? m : 0;
+            V[b].nx = T[b].nx + 2 * m; V[b].ny = T[b].ny + 2 * m; V[b].nz = T[b].nz + 2 * mz;
+            V[b].ng = ngt - m;           /* same memory and strides; interior grown by m */
+            V[b].offset = T[b].offset;
+        }
+        ora_problem Q = *P;
+        Q.blocks = V;
+        Q.ncell = nct;
+        bad += ora_r_stage(&Q, s, *dt, Un, in, out);
+        in = out;
+        out = (out == Ua) ? Ub : Ua;
+    }
+    if (!bad)
+        for (int b = 0; b < P->nblocks; b++) {
+            const ora_block *B = &P->blocks[b];
+            for (int k = 0; k < B->nz; k++)
+                for (int j = 0; j < B->ny; j++)
+                    for (int i = 0; i < B->nx; i++)
+                        for (int v = 0; v < nv; v++)
+                            U[v * P->ncell + ora_r_cell(B, P->ndim, i, j, k)] = in[v * nct + ora_r_cell(&T[b], P->ndim, i, j, k)];
+        }
+    free(T); free(V); free(Un); free(Ua); free(Ub);
+    return bad ? ORA_ENONPHYS : ORA_OK;
+}
+
 /* ------------------------------------------------------------- adjoint */
 
 /* Reverse of the EOS: gU (nvar) += (dW/dU)^T gW. */

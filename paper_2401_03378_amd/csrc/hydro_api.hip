@@ -52,6 +52,16 @@ struct hydro_ctx {
     int *d_inc_start = nullptr;
     int4 *d_inc = nullptr;
     double *d_vjp = nullptr;     // gW | gA | gB, each nvar x ncell
+    // telescoping: thick block copies, per-stage virtual (extended) blocks and work lists
+    int tele_ready = 0;
+    int ngt = 0;
+    int64_t ncell_t = 0;
+    DevBlock *d_tblocks = nullptr;
+    FaceSrc *d_tfaces = nullptr;
+    DevBlock *d_vblocks[3] = {nullptr, nullptr, nullptr};
+    WorkItem *d_titems[3] = {nullptr, nullptr, nullptr};
+    int ntitems[3] = {0, 0, 0};
+    double *d_tbuf = nullptr;    // U^n | A | B in the thick layout
 };
 
 namespace {
@@ -351,8 +361,11 @@ int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const
 
 // Stage buffers: RK2 U -> B0 -> U ; RK3 U -> B0 -> B1 -> U.  The final stage
 // writes U in place (it reads U^n only at the cell it writes).
+int enqueue_step_tele(hydro_ctx *c, double *U, double *dt, int compute_dt, hipStream_t st);
+
 int enqueue_step(hydro_ctx *c, double *U, double *dt, int compute_dt, hipStream_t st)
 {
+    if (c->tune.mode == HYDRO_MODE_TELESCOPING) return enqueue_step_tele(c, U, dt, compute_dt, st);
     int rc;
     if (compute_dt && (rc = enqueue_cfl(c, U, dt, st))) return rc;
     const int S = c->prm.rk;
@@ -437,6 +450,159 @@ int setup_vjp(hydro_ctx *c)
         c->d_vjp = nullptr;
         return fail(c, HYDRO_ENOMEM, "adjoint scratch");
     }
+    return HYDRO_OK;
+}
+
+// Telescoping step tables (built when that mode is selected).
+int setup_tele(hydro_ctx *c)
+{
+    const int nd = c->prm.ndim, S = c->prm.rk;
+    const int H = (c->prm.recon == HYDRO_WENO5) ? 3 : 2;
+    const int ngt = S * H;
+    for (int b = 0; b < c->nblocks; ++b)
+        for (int d = 0; d < nd; ++d)
+            for (int side = 0; side < 2; ++side) {
+                const int nb = c->hl[b].nbr[2 * d + side];
+                const hydro_block_t &Src = (nb >= 0) ? c->hb[nb] : c->hb[b];
+                if (nb != HYDRO_OUTFLOW && extent(Src, d) < ngt)
+                    return fail(c, HYDRO_EINVAL, "telescoping halo (" + std::to_string(ngt) +
+                                " layers) deeper than a source block");
+            }
+    if (c->tele_ready) return HYDRO_OK;
+    std::vector<DevBlock> tb(c->nblocks);
+    int64_t off = 0;
+    for (int b = 0; b < c->nblocks; ++b) {
+        const hydro_block_t &B = c->hb[b];
+        DevBlock D{};
+        D.off = off;
+        D.nx = B.nx; D.ny = B.ny; D.nz = B.nz; D.ng = ngt;
+        D.px = B.nx + 2 * ngt;
+        D.py = B.ny + 2 * ngt;
+        D.gz = (nd == 3) ? ngt : 0;
+        tb[b] = D;
+        off += (int64_t)D.px * D.py * ((nd == 3) ? B.nz + 2 * ngt : 1);
+    }
+    c->ncell_t = off;
+    c->ngt = ngt;
+    std::vector<FaceSrc> tf((size_t)c->nblocks * 6, FaceSrc{0, 0, 0, 0, 0});
+    for (int b = 0; b < c->nblocks; ++b)
+        for (int d = 0; d < nd; ++d)
+            for (int side = 0; side < 2; ++side) {
+                const int nb = c->hl[b].nbr[2 * d + side];
+                const int n = extent(c->hb[b], d);
+                const int src = (nb >= 0) ? nb : b;
+                FaceSrc f{};
+                f.off = tb[src].off;
+                f.px = tb[src].px;
+                f.py = tb[src].py;
+                if (nb == HYDRO_OUTFLOW) { f.A = (side == 0) ? 0 : n - 1; f.B = 0; }
+                else { f.A = (side == 0) ? extent(c->hb[src], d) : -n; f.B = 1; }
+                tf[(size_t)b * 6 + 2 * d + side] = f;
+            }
+    HIP_TRY(c, hipMalloc(&c->d_tblocks, sizeof(DevBlock) * std::max(1, c->nblocks)));
+    HIP_TRY(c, hipMalloc(&c->d_tfaces, sizeof(FaceSrc) * std::max(1, c->nblocks) * 6));
+    if (c->nblocks) {
+        HIP_TRY(c, hipMemcpy(c->d_tblocks, tb.data(), sizeof(DevBlock) * c->nblocks, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_tfaces, tf.data(), sizeof(FaceSrc) * c->nblocks * 6, hipMemcpyHostToDevice));
+    }
+    const int TX = tile_x(c->tune.tile), TY = tile_y(c->tune.tile);
+    for (int s = 1; s <= S; ++s) {
+        const int m = (S - s) * H;
+        std::vector<DevBlock> vb(c->nblocks);
+        std::vector<WorkItem> items;
+        for (int b = 0; b < c->nblocks; ++b) {
+            DevBlock V = tb[b];
+            V.nx += 2 * m;
+            V.ny += 2 * m;
+            if (nd == 3) V.nz += 2 * m;
+            V.ng = ngt - m;
+            V.gz = (nd == 3) ? ngt - m : 0;
+            vb[b] = V;
+            for (int y0 = 0; y0 < V.ny; y0 += TY)
+                for (int x0 = 0; x0 < V.nx; x0 += TX) {
+                    WorkItem w{};
+                    w.block = b;
+                    w.xy = x0 | (y0 << 16);
+                    w.z = 0 | (V.nz << 16);
+                    w.cost = std::min(TX, V.nx - x0) * std::min(TY, V.ny - y0) * V.nz;
+                    items.push_back(w);
+                }
+        }
+        std::stable_sort(items.begin(), items.end(), [](const WorkItem &x, const WorkItem &y) { return x.cost > y.cost; });
+        HIP_TRY(c, hipMalloc(&c->d_vblocks[s - 1], sizeof(DevBlock) * std::max(1, c->nblocks)));
+        HIP_TRY(c, hipMalloc(&c->d_titems[s - 1], sizeof(WorkItem) * std::max<size_t>(1, items.size())));
+        if (c->nblocks)
+            HIP_TRY(c, hipMemcpy(c->d_vblocks[s - 1], vb.data(), sizeof(DevBlock) * c->nblocks, hipMemcpyHostToDevice));
+        if (!items.empty())
+            HIP_TRY(c, hipMemcpy(c->d_titems[s - 1], items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
+        c->ntitems[s - 1] = (int)items.size();
+    }
+    const size_t per = (size_t)c->nv * (size_t)std::max<int64_t>(1, c->ncell_t);
+    if (hipMalloc(&c->d_tbuf, sizeof(double) * per * (S == 3 ? 3 : 2)) != hipSuccess) {
+        c->d_tbuf = nullptr;
+        return fail(c, HYDRO_ENOMEM, "telescoping buffers");
+    }
+    c->tele_ready = 1;
+    return HYDRO_OK;
+}
+
+void free_tele(hydro_ctx *c)
+{
+    (void)hipFree(c->d_tblocks);
+    (void)hipFree(c->d_tfaces);
+    for (int s = 0; s < 3; ++s) {
+        (void)hipFree(c->d_vblocks[s]);
+        (void)hipFree(c->d_titems[s]);
+        c->d_vblocks[s] = nullptr;
+        c->d_titems[s] = nullptr;
+        c->ntitems[s] = 0;
+    }
+    (void)hipFree(c->d_tbuf);
+    c->d_tblocks = nullptr;
+    c->d_tfaces = nullptr;
+    c->d_tbuf = nullptr;
+    c->tele_ready = 0;
+}
+
+// Telescoping step: CFL dt on U, one thick fill, S stages on the shrinking
+// extended blocks (the last writes the thick U^n copy in place), copy back.
+int enqueue_step_tele(hydro_ctx *c, double *U, double *dt, int compute_dt, hipStream_t st)
+{
+    int rc;
+    if (compute_dt && (rc = enqueue_cfl(c, U, dt, st))) return rc;
+    const int nd = c->prm.ndim, S = c->prm.rk;
+    const size_t per = (size_t)c->nv * (size_t)c->ncell_t;
+    double *Tn = c->d_tbuf, *TA = c->d_tbuf + per, *TB = (S == 3) ? c->d_tbuf + 2 * per : nullptr;
+    TeleArgs t{};
+    t.tb = c->d_tblocks;
+    t.tf = c->d_tfaces;
+    t.ub = c->d_blocks;
+    t.nct = c->ncell_t;
+    t.ncu = c->ncell;
+    t.T = Tn;
+    t.U = U;
+    hipError_t e = launch_tele_copy(t, nd, c->nblocks, true, st);
+    if (e != hipSuccess) return hip_fail(c, e, "telescoping load");
+    for (int d = 0; d < nd; ++d) {
+        t.d = d;
+        e = launch_tele_fill(t, nd, c->nblocks, st);
+        if (e != hipSuccess) return hip_fail(c, e, "telescoping fill");
+    }
+    const double *in = Tn;
+    for (int s = 1; s <= S; ++s) {
+        double *out = (s == S) ? Tn : ((s == 1) ? TA : TB);
+        StageArgs a = stage_args(c, s, dt, Tn, in, out);
+        a.blocks = c->d_vblocks[s - 1];
+        a.items = c->d_titems[s - 1];
+        a.nitems = c->ntitems[s - 1];
+        a.nc = c->ncell_t;
+        const int grid = c->tune.grid > 0 ? std::min(c->tune.grid, a.nitems) : a.nitems;
+        e = launch_stage(a, nd, c->prm.recon, c->tune.tile, false, grid, st);
+        if (e != hipSuccess) return hip_fail(c, e, "telescoping stage launch");
+        in = out;
+    }
+    e = launch_tele_copy(t, nd, c->nblocks, false, st);
+    if (e != hipSuccess) return hip_fail(c, e, "telescoping store");
     return HYDRO_OK;
 }
 
@@ -529,12 +695,24 @@ int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks, cons
 int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
 {
     if (!c || !t) return HYDRO_EINVAL;
-    if (t->mode != HYDRO_MODE_PERSISTENT && t->mode != HYDRO_MODE_PERBLOCK) return fail(c, HYDRO_EINVAL, "mode");
+    if (t->mode != HYDRO_MODE_PERSISTENT && t->mode != HYDRO_MODE_PERBLOCK && t->mode != HYDRO_MODE_TELESCOPING)
+        return fail(c, HYDRO_EINVAL, "mode");
     if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0) return fail(c, HYDRO_EINVAL, "tuning range");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
+    const int old_tile = c->tune.tile;
     c->tune = *t;
-    return upload_items(c);
+    int rc = upload_items(c);
+    if (rc) return rc;
+    if (c->tele_ready && old_tile != t->tile) free_tele(c);
+    if (t->mode == HYDRO_MODE_TELESCOPING) {
+        rc = setup_tele(c);
+        if (rc) {
+            c->tune.mode = HYDRO_MODE_PERSISTENT;
+            return rc;
+        }
+    }
+    return HYDRO_OK;
 }
 
 int hydro_get_tuning(hydro_ctx_t *c, hydro_tuning_t *t)
@@ -562,6 +740,8 @@ int hydro_rk_stage(hydro_ctx_t *c, int32_t stage, const double *dt_dev, const do
 {
     if (!c || !dt_dev || !Un || !Us || !Uout) return fail(c, HYDRO_EINVAL, "null pointer");
     if (stage < 1 || stage > c->prm.rk) return fail(c, HYDRO_EINVAL, "stage out of range");
+    if (c->tune.mode == HYDRO_MODE_TELESCOPING)
+        return fail(c, HYDRO_EINVAL, "single stages are not defined in the telescoping mode");
     if (Uout == Us) return fail(c, HYDRO_EINVAL, "Uout aliases Us");
     return enqueue_stage(c, stage, dt_dev, Un, Us, Uout, c->stream);
 }
@@ -602,6 +782,8 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
 {
     if (!c || !Un || !dt_dev || !gUnext || !gUn) return fail(c, HYDRO_EINVAL, "null pointer");
     if (gUn == gUnext) return fail(c, HYDRO_EINVAL, "gUn aliases gUnext");
+    if (c->tune.mode == HYDRO_MODE_TELESCOPING)
+        return fail(c, HYDRO_EINVAL, "the adjoint is defined for the per-stage-fill step only");
     if (c->nitems == 0) return HYDRO_OK;
     int rc = setup_vjp(c);
     if (rc) return rc;
@@ -699,6 +881,7 @@ void hydro_destroy(hydro_ctx_t *c)
     (void)hipFree(c->d_citems);
     (void)hipFree(c->d_inc_start);
     (void)hipFree(c->d_inc);
+    free_tele(c);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
 }

@@ -346,6 +346,86 @@ __global__ void __launch_bounds__(256) k_fill_guards(GuardArgs A)
     }
 }
 
+// ------------------------------------------------------- telescoping step
+//
+// The paper's telescoping RK variant (Sec. 4.2, second listing): one guard
+// fill per step into thick copies of the blocks, then every stage updates the
+// block and the part of its halo later stages still read.  The thick halo is
+// filled one direction after the other (one launch per direction): direction
+// d copies ng layers over the already-filled extents of the directions
+// before it, so edges and corners come from neighbours of neighbours.
+
+// Interior copy between the caller's layout and the thick layout.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_tele_copy(TeleArgs A, int to_thick)
+{
+    const int b = blockIdx.x;
+    const DevBlock Bt = A.tb[b], Bu = A.ub[b];
+    const int n = Bu.nx * Bu.ny * Bu.nz;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int i = q % Bu.nx, j = (q / Bu.nx) % Bu.ny, k = q / (Bu.nx * Bu.ny);
+        const int64_t ct = cell_at(Bt, i, j, k), cu = cell_at(Bu, i, j, k);
+#pragma unroll
+        for (int v = 0; v < NDIM + 2; ++v) {
+            if (to_thick) A.T[v * A.nct + ct] = A.U[v * A.ncu + cu];
+            else A.U[v * A.ncu + cu] = A.T[v * A.nct + ct];
+        }
+    }
+}
+
+// Halo layers of direction A.d: workgroup = (block, side).
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_tele_fill(TeleArgs A)
+{
+    const int b = blockIdx.x / 2, side = blockIdx.x % 2, d = A.d;
+    const DevBlock B = A.tb[b];
+    const FaceSrc S = A.tf[6 * (int64_t)b + 2 * d + side];
+    const int g = B.ng;
+    const int n3[3] = {B.nx, B.ny, B.nz};
+    int lo[3], len[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        if (e >= NDIM || e == d) { lo[e] = 0; len[e] = 1; }
+        else if (e < d) { lo[e] = -g; len[e] = n3[e] + 2 * g; }
+        else { lo[e] = 0; len[e] = n3[e]; }
+    }
+    const int n = n3[d];
+    const int plane = len[0] * len[1] * len[2];
+    const int count = g * plane;
+    for (int q = threadIdx.x; q < count; q += blockDim.x) {
+        const int l = q / plane + 1;
+        const int r = q % plane;
+        int c[3];
+        c[0] = lo[0] + r % len[0];
+        c[1] = lo[1] + (r / len[0]) % len[1];
+        c[2] = lo[2] + r / (len[0] * len[1]);
+        const int pos = (side == 0) ? -l : n - 1 + l;
+        int s[3] = {c[0], c[1], c[2]};
+        c[d] = pos;
+        s[d] = S.A + S.B * pos;
+        const int64_t gi = cell_at(B, c[0], c[1], c[2]);
+        const int64_t si = S.off + ((int64_t)(s[2] + B.gz) * S.py + (s[1] + B.ng)) * S.px + (s[0] + B.ng);
+#pragma unroll
+        for (int v = 0; v < NDIM + 2; ++v) A.T[v * A.nct + gi] = A.T[v * A.nct + si];
+    }
+}
+
+hipError_t launch_tele_fill(const TeleArgs &a, int ndim, int nblk, hipStream_t st)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (ndim == 3) k_tele_fill<3><<<2 * nblk, 256, 0, st>>>(a);
+    else k_tele_fill<2><<<2 * nblk, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick, hipStream_t st)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (ndim == 3) k_tele_copy<3><<<nblk, 256, 0, st>>>(a, to_thick ? 1 : 0);
+    else k_tele_copy<2><<<nblk, 256, 0, st>>>(a, to_thick ? 1 : 0);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- launchers
 
 template <int NDIM, int RECON, int TX, int TY, bool GATHER>

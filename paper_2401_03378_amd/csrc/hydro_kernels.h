@@ -40,6 +40,17 @@ struct GuardArgs {
     double *U;
 };
 
+// Telescoping step: thick copies of the blocks (T) and the caller's layout (U).
+struct TeleArgs {
+    const DevBlock *tb;         // thick blocks (ng = halo width of the step)
+    const FaceSrc *tf;          // per face: source of the thick halo layers
+    const DevBlock *ub;         // blocks in the caller's layout
+    int64_t nct, ncu;           // cells per variable plane: thick, caller
+    int32_t d;                  // direction filled by this launch
+    double *T;
+    double *U;
+};
+
 struct VjpArgs {
     const DevBlock *blocks;
     const FaceSrc *faces;
@@ -64,6 +75,8 @@ struct VjpArgs {
 hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, bool gather, int grid, hipStream_t st);
 hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl, double *dt, hipStream_t st);
 hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st);
+hipError_t launch_tele_fill(const TeleArgs &a, int ndim, int nblk, hipStream_t st);
+hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick, hipStream_t st);
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st);
 hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st);
 hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st);
