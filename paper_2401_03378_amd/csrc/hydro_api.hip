@@ -45,13 +45,13 @@ struct hydro_ctx {
     const double *g_dt = nullptr;
     int g_cdt = -1;
     // adjoint: line work lists per direction, 8x8 cell tiles, inverse links, scratch
-    WorkItem *d_lines[3] = {nullptr, nullptr, nullptr};
-    int nlines[3] = {0, 0, 0};
+    WorkItem *d_lines = nullptr;  // lines of every direction (cost field = direction)
+    int nlines = 0;
     WorkItem *d_citems = nullptr;
     int ncitems = 0;
     int *d_inc_start = nullptr;
     int4 *d_inc = nullptr;
-    double *d_vjp = nullptr;     // gW | gA | gB, each nvar x ncell
+    double *d_vjp = nullptr;     // gW_x | gW_y [| gW_z] | gA | gB, each nvar x ncell
     // telescoping: thick block copies, per-stage virtual (extended) blocks and work lists
     int tele_ready = 0;
     int ngt = 0;
@@ -384,8 +384,8 @@ int setup_vjp(hydro_ctx *c)
     if (c->d_vjp) return HYDRO_OK;
     const int nd = c->prm.ndim;
     // lines along each direction, grouped by 64 within a block
+    std::vector<WorkItem> v;
     for (int d = 0; d < nd; ++d) {
-        std::vector<WorkItem> v;
         for (int b = 0; b < c->nblocks; ++b) {
             const hydro_block_t &B = c->hb[b];
             const int n1 = (d == 0) ? B.ny : B.nx;
@@ -396,15 +396,15 @@ int setup_vjp(hydro_ctx *c)
                 w.block = b;
                 w.xy = l0;
                 w.z = std::min(64, nl - l0);
-                w.cost = 0;
+                w.cost = d;
                 v.push_back(w);
             }
         }
-        c->nlines[d] = (int)v.size();
-        HIP_TRY(c, hipMalloc(&c->d_lines[d], sizeof(WorkItem) * std::max<size_t>(1, v.size())));
-        if (!v.empty())
-            HIP_TRY(c, hipMemcpy(c->d_lines[d], v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
     }
+    c->nlines = (int)v.size();
+    HIP_TRY(c, hipMalloc(&c->d_lines, sizeof(WorkItem) * std::max<size_t>(1, v.size())));
+    if (!v.empty())
+        HIP_TRY(c, hipMemcpy(c->d_lines, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
     // cell tiles 8x8 over whole z columns
     std::vector<WorkItem> ci;
     for (int b = 0; b < c->nblocks; ++b) {
@@ -446,7 +446,7 @@ int setup_vjp(hydro_ctx *c)
     if (!flat.empty())
         HIP_TRY(c, hipMemcpy(c->d_inc, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice));
     const size_t per = (size_t)c->nv * (size_t)std::max<int64_t>(1, c->ncell);
-    if (hipMalloc(&c->d_vjp, sizeof(double) * per * 3) != hipSuccess) {
+    if (hipMalloc(&c->d_vjp, sizeof(double) * per * (size_t)(nd + 2)) != hipSuccess) {
         c->d_vjp = nullptr;
         return fail(c, HYDRO_ENOMEM, "adjoint scratch");
     }
@@ -798,7 +798,7 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         if (e != hipSuccess) return hip_fail(c, e, "stage launch");
     }
     HIP_TRY(c, hipMemsetAsync(gUn, 0, sizeof(double) * per, st));
-    double *gW = c->d_vjp, *gbuf[2] = {c->d_vjp + per, c->d_vjp + 2 * per};
+    double *gW = c->d_vjp, *gbuf[2] = {c->d_vjp + nd * per, c->d_vjp + (nd + 1) * per};
     const double *g = gUnext;
     for (int s = S, q = 0; s >= 1; --s, q ^= 1) {
         VjpArgs v{};
@@ -822,12 +822,10 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         v.gUn = (s >= 2) ? gUn : nullptr;
         v.inc_start = c->d_inc_start;
         v.inc = c->d_inc;
-        for (int d = 0; d < nd; ++d) {
-            v.items = c->d_lines[d];
-            v.nitems = c->nlines[d];
-            hipError_t e = launch_vjp_lines(v, nd, c->prm.recon, d, c->nlines[d], st);
-            if (e != hipSuccess) return hip_fail(c, e, "adjoint line launch");
-        }
+        v.items = c->d_lines;
+        v.nitems = c->nlines;
+        hipError_t el = launch_vjp_lines(v, nd, c->prm.recon, 0, c->nlines, st);
+        if (el != hipSuccess) return hip_fail(c, el, "adjoint line launch");
         hipError_t e = launch_vjp_cells(v, nd, c->prm.recon, c->ncitems, st);
         if (e != hipSuccess) return hip_fail(c, e, "adjoint cell launch");
         g = gbuf[q];
@@ -877,7 +875,7 @@ void hydro_destroy(hydro_ctx_t *c)
     (void)hipFree(c->d_partial);
     (void)hipFree(c->d_nbad);
     (void)hipFree(c->d_vjp);
-    for (int d = 0; d < 3; ++d) (void)hipFree(c->d_lines[d]);
+    (void)hipFree(c->d_lines);
     (void)hipFree(c->d_citems);
     (void)hipFree(c->d_inc_start);
     (void)hipFree(c->d_inc);

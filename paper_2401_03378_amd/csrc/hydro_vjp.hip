@@ -5,15 +5,16 @@
 //
 // A stage is U_{s+1} = b (U_s + dt L(U_s)) + a U^n with
 // L = -sum_d (F_{d,i+1/2} - F_{d,i-1/2})/dx_d.  Its transpose splits into
-//  k_vjp_lines<D>  one thread per 1D line of a block along direction D,
-//                  streaming along the line: it recomputes primitives,
-//                  reconstruction (with fallback) and the HLLC branch, then
-//                  reverses face flux -> face states -> stencil primitives,
-//                  and writes the primitive cotangent gW of every position the
-//                  line's stencils read (interior and guard positions) into a
-//                  padded array.  Directions run as successive launches, so
-//                  interior sums are race-free and in a fixed order.
-//  k_vjp_cells     one thread per interior cell: adds the cotangents of the
+//  k_vjp_lines     one thread per 1D line of a block (every direction in one
+//                  launch), streaming along the line: it recomputes
+//                  primitives, reconstruction (with fallback) and the HLLC
+//                  branch, then reverses face flux -> face states -> stencil
+//                  primitives, and writes the primitive cotangent of every
+//                  position the line's stencils read (interior and guard
+//                  positions) into a padded array of its own direction, so no
+//                  two threads write one element.
+//  k_vjp_cells     one thread per interior cell: sums the directions' arrays
+//                  in the order x, y, z, adds the cotangents of the
 //                  guard positions that are copies of the cell (through the
 //                  inverse link table; neighbour, periodic and outflow
 //                  copies), applies the EOS transpose and forms
@@ -305,15 +306,13 @@ __device__ __forceinline__ void line_coords(int t, int e1, int e2, int &i, int &
 }
 
 template <int NDIM, int RECON, int D>
-__global__ void __launch_bounds__(64) k_vjp_lines(VjpArgs A)
+__device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, int lane)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
     constexpr int H = R + 1;
     constexpr int NV = NDIM + 2;
     constexpr int NS = 2 * R + 1;     // stencil
     constexpr int NWIN = 2 * R + 2;   // primitives at positions t-2R-1 .. t
-    const WorkItem it = A.items[blockIdx.x];
-    const int lane = threadIdx.x;
     const int nl = it.z;               // lines in this item
     if (lane >= nl) return;
     const DevBlock B = A.blocks[it.block];
@@ -342,17 +341,15 @@ __global__ void __launch_bounds__(64) k_vjp_lines(VjpArgs A)
 #pragma unroll
     for (int v = 0; v < 5; ++v) { qp_prev[v] = 0.0; gqm_prev[v] = 0.0; gD_prev[v] = 0.0; }
 
+    double *gWd = A.gW + (int64_t)D * NV * nc;      // this direction's array
     auto emit = [&](int p, const double (&gw)[5]) {
         int i, j, k;
         line_coords<D>(p, e1, e2, i, j, k);
         const int64_t ci = cell_at(B, i, j, k);
-        const bool inner = (p >= 0 && p < n);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             if (NDIM == 2 && v == 3) continue;
-            double *dst = A.gW + (int64_t)wslot<NDIM>(v) * nc + ci;
-            if (D == 0 || !inner) *dst = gw[v];
-            else *dst = *dst + gw[v];
+            gWd[(int64_t)wslot<NDIM>(v) * nc + ci] = gw[v];
         }
     };
 
@@ -441,6 +438,16 @@ __global__ void __launch_bounds__(64) k_vjp_lines(VjpArgs A)
     }
 }
 
+// One launch for every direction: work item cost field = direction.
+template <int NDIM, int RECON>
+__global__ void __launch_bounds__(64) k_vjp_lines(VjpArgs A)
+{
+    const WorkItem it = A.items[blockIdx.x];
+    if (it.cost == 0) vjp_line<NDIM, RECON, 0>(A, it, threadIdx.x);
+    else if (it.cost == 1) vjp_line<NDIM, RECON, 1>(A, it, threadIdx.x);
+    else if constexpr (NDIM == 3) vjp_line<NDIM, RECON, 2>(A, it, threadIdx.x);
+}
+
 // ------------------------------------------------------------ cell kernel
 
 // Reverse of the EOS at one cell: gU (nvar) = (dW/dU)^T gW.
@@ -482,8 +489,13 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
             double gw[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) gw[v] = 0.0;
+            const int64_t dstride = (int64_t)NV * nc;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] = A.gW[v * nc + ci];
+            for (int v = 0; v < NV; ++v) {
+                double t = A.gW[v * nc + ci] + A.gW[dstride + v * nc + ci];
+                if constexpr (NDIM == 3) t = t + A.gW[2 * dstride + v * nc + ci];
+                gw[v == NDIM + 1 ? 4 : v] = t;
+            }
             // guard positions (of this or other blocks) that copy this cell
             for (int e = inc0; e < inc1; ++e) {
                 const int4 q = A.inc[e];                 // x = block, y = dir, z = side, w = kind
@@ -505,7 +517,7 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
                     const int gi = (d == 0) ? gpos : i, gj = (d == 1) ? gpos : j, gk = (d == 2) ? gpos : k;
                     const int64_t gc = cell_at(X, gi, gj, gk);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] += A.gW[v * nc + gc];
+                    for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] += A.gW[d * dstride + v * nc + gc];
                 }
             }
             double u[5], gu[5];
@@ -545,23 +557,18 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_add(VjpArgs A)
 
 // ------------------------------------------------------------- launchers
 
-template <int NDIM, int RECON>
-static hipError_t launch_vjp_lines_r(const VjpArgs &a, int d, int nitems, hipStream_t st)
-{
-    if (nitems <= 0) return hipSuccess;
-    if (d == 0) k_vjp_lines<NDIM, RECON, 0><<<nitems, 64, 0, st>>>(a);
-    else if (d == 1) k_vjp_lines<NDIM, RECON, 1><<<nitems, 64, 0, st>>>(a);
-    else if constexpr (NDIM == 3) k_vjp_lines<NDIM, RECON, 2><<<nitems, 64, 0, st>>>(a);
-    return hipGetLastError();
-}
-
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st)
 {
-    if (ndim == 3)
-        return recon == kWENO ? launch_vjp_lines_r<3, kWENO>(a, d, nitems, st)
-                              : launch_vjp_lines_r<3, kPLM>(a, d, nitems, st);
-    return recon == kWENO ? launch_vjp_lines_r<2, kWENO>(a, d, nitems, st)
-                          : launch_vjp_lines_r<2, kPLM>(a, d, nitems, st);
+    (void)d;
+    if (nitems <= 0) return hipSuccess;
+    if (ndim == 3) {
+        if (recon == kWENO) k_vjp_lines<3, kWENO><<<nitems, 64, 0, st>>>(a);
+        else k_vjp_lines<3, kPLM><<<nitems, 64, 0, st>>>(a);
+    } else {
+        if (recon == kWENO) k_vjp_lines<2, kWENO><<<nitems, 64, 0, st>>>(a);
+        else k_vjp_lines<2, kPLM><<<nitems, 64, 0, st>>>(a);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st)
