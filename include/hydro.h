@@ -92,6 +92,7 @@ typedef struct {
     int32_t zchunk;     /* z planes per work item; 0 = the whole block */
     int32_t use_graph;  /* replay hydro_step from a captured hipGraph */
     int32_t xcd;        /* place a block's work items on one XCD (L2) */
+    int32_t variant;    /* stage schedule: 0 plain, 1 loads of the next plane issued a plane ahead */
 } hydro_tuning_t;
 
 typedef struct hydro_ctx hydro_ctx_t;

@@ -46,7 +46,8 @@ class Params(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("mode", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32),
-                ("zchunk", C.c_int32), ("use_graph", C.c_int32), ("xcd", C.c_int32)]
+                ("zchunk", C.c_int32), ("use_graph", C.c_int32), ("xcd", C.c_int32),
+                ("variant", C.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -1,7 +1,8 @@
 """Autotuner for the stage launch configuration.
 
-Searches tile shape (8x8, 16x8, 16x16 columns per work item), z-chunking of
-work items, the persistent grid size and the XCD placement of a block's work
+Searches the stage-kernel schedule (plain, or loads issued one plane ahead),
+tile shape (8x8, 16x8, 16x16 columns per work item), z-chunking of work
+items, the persistent grid size and the XCD placement of a block's work
 items.  Every candidate must reproduce the reference candidate's state bit
 for bit after two steps (the kernels are deterministic and the launch shape
 must not change a single rounding), then the fastest by timed steps wins.
@@ -35,13 +36,15 @@ def signature(prob, arch=None) -> str:
 def candidates(prob, ncu):
     out = []
     zch = [0] if prob.ndim == 2 else [0, 8]
-    for tile in (0, 1, 2):
-        for zc in zch:
-            for grid in (0, 2 * ncu, 4 * ncu):
-                for xcd in (0, 1):
-                    if xcd and grid == 0:
-                        continue
-                    out.append(dict(mode=0, tile=tile, zchunk=zc, grid=grid, xcd=xcd, use_graph=1))
+    for variant in (0, 1):
+        for tile in (0, 1, 2):
+            for zc in zch:
+                for grid in (0, 2 * ncu, 4 * ncu):
+                    for xcd in (0, 1):
+                        if xcd and grid == 0:
+                            continue
+                        out.append(dict(mode=0, tile=tile, zchunk=zc, grid=grid, xcd=xcd, use_graph=1,
+                                        variant=variant))
     return out
 
 

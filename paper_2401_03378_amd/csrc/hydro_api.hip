@@ -349,12 +349,12 @@ int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const
             if (rc) return rc;
             a.items = c->d_items_pb + c->pb_start[b];
             a.nitems = c->pb_start[b + 1] - c->pb_start[b];
-            hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, false, a.nitems, st);
+            hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, c->tune.variant, false, a.nitems, st);
             if (e != hipSuccess) return hip_fail(c, e, "stage launch");
         }
         return HYDRO_OK;
     }
-    hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, true, persistent_grid(c), st);
+    hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, c->tune.variant, true, persistent_grid(c), st);
     if (e != hipSuccess) return hip_fail(c, e, "stage launch");
     return HYDRO_OK;
 }
@@ -597,7 +597,7 @@ int enqueue_step_tele(hydro_ctx *c, double *U, double *dt, int compute_dt, hipSt
         a.nitems = c->ntitems[s - 1];
         a.nc = c->ncell_t;
         const int grid = c->tune.grid > 0 ? std::min(c->tune.grid, a.nitems) : a.nitems;
-        e = launch_stage(a, nd, c->prm.recon, c->tune.tile, false, grid, st);
+        e = launch_stage(a, nd, c->prm.recon, c->tune.tile, c->tune.variant, false, grid, st);
         if (e != hipSuccess) return hip_fail(c, e, "telescoping stage launch");
         in = out;
     }
@@ -686,6 +686,7 @@ int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks, cons
     c->tune.zchunk = 0;
     c->tune.use_graph = 1;
     c->tune.xcd = 0;
+    c->tune.variant = 0;
     int rc = upload_items(c);
     if (rc) return bail(rc);
     *out = c;
@@ -697,7 +698,8 @@ int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
     if (!c || !t) return HYDRO_EINVAL;
     if (t->mode != HYDRO_MODE_PERSISTENT && t->mode != HYDRO_MODE_PERBLOCK && t->mode != HYDRO_MODE_TELESCOPING)
         return fail(c, HYDRO_EINVAL, "mode");
-    if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0) return fail(c, HYDRO_EINVAL, "tuning range");
+    if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0 || t->variant < 0 || t->variant > 1)
+        return fail(c, HYDRO_EINVAL, "tuning range");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     const int old_tile = c->tune.tile;
@@ -794,7 +796,7 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
     const double *Us_of[4] = {nullptr, Un, c->d_buf[0], c->d_buf[1]};
     for (int s = 1; s < S; ++s) {
         StageArgs a = stage_args(c, s, dt_dev, Un, Us_of[s], c->d_buf[s - 1]);
-        hipError_t e = launch_stage(a, nd, c->prm.recon, c->tune.tile, true, persistent_grid(c), st);
+        hipError_t e = launch_stage(a, nd, c->prm.recon, c->tune.tile, c->tune.variant, true, persistent_grid(c), st);
         if (e != hipSuccess) return hip_fail(c, e, "stage launch");
     }
     HIP_TRY(c, hipMemsetAsync(gUn, 0, sizeof(double) * per, st));

@@ -25,7 +25,7 @@
 
 namespace hydro {
 
-template <int NDIM, int RECON, int TX, int TY, bool GATHER>
+template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF>
 __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
@@ -62,6 +62,43 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
         double zw[NW][5];     // primitives of cells k+1-R .. k+1+R along z
         double qpz[5];        // right-face state of cell k (z)
         double Flo[5];        // z flux at k-1/2
+        // prefetch schedule (PF): raw values of the next plane, loaded one plane ahead
+        constexpr int NSLOT = (2 * H * (TX + TY) + NT - 1) / NT;
+        double pz[5], ph[NSLOT][5], pus[5], pun[5];
+        auto halo_cell = [&](int e, int k, int &li, int &lj) -> int64_t {
+            if (e < 2 * H * wy) {
+                const int row = e / (2 * H), c = e % (2 * H);
+                const int off = (c < H) ? c - H : wx + (c - H);
+                li = off + H;
+                lj = row + H;
+                return src_cell<0, GATHER>(B, F6, x0 + off, y0 + row, k);
+            }
+            const int e2 = e - 2 * H * wy;
+            const int c = e2 / wx, col = e2 % wx;
+            const int off = (c < H) ? c - H : wy + (c - H);
+            li = col + H;
+            lj = off + H;
+            return src_cell<1, GATHER>(B, F6, x0 + col, y0 + off, k);
+        };
+        auto prefetch = [&](int k) {
+            if (own) {
+                if constexpr (NDIM == 3)
+                    load_cons<NDIM>(A.Us, nc, src_cell<2, GATHER>(B, F6, i, j, k + H), pz);
+                else
+                    load_cons<NDIM>(A.Us, nc, cell_at(B, i, j, k), pz);
+                const int64_t ci = cell_at(B, i, j, k);
+                load_cons<NDIM>(A.Us, nc, ci, pus);
+                if (A.stage != 1) load_cons<NDIM>(A.Un, nc, ci, pun);
+            }
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q) {
+                const int e = tid + q * NT;
+                if (e < nhalo) {
+                    int li, lj;
+                    load_cons<NDIM>(A.Us, nc, halo_cell(e, k, li, lj), ph[q]);
+                }
+            }
+        };
         if constexpr (NDIM == 3) {
             if (own) {
                 double Wt[NW + 1][5];
@@ -89,13 +126,29 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
             }
         }
 
+        if constexpr (PF) prefetch(z0);
         for (int kk = 0; kk < nzc; ++kk) {
             const int k = z0 + kk;
             double Dz[5];
+            double cus[5], cun[5], chalo[NSLOT][5], cz[5];
+            if constexpr (PF) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) { cus[v] = pus[v]; cun[v] = pun[v]; cz[v] = pz[v]; }
+#pragma unroll
+                for (int q = 0; q < NSLOT; ++q)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) chalo[q][v] = ph[q][v];
+                if (kk + 1 < nzc) prefetch(k + 1);
+            }
             if (own) {
                 if constexpr (NDIM == 3) {
                     double u[5];
-                    load_cons<NDIM>(A.Us, nc, src_cell<2, GATHER>(B, F6, i, j, k + H), u);
+                    if constexpr (PF) {
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) u[v] = cz[v];
+                    } else {
+                        load_cons<NDIM>(A.Us, nc, src_cell<2, GATHER>(B, F6, i, j, k + H), u);
+                    }
                     bad |= eos<NDIM>(u, zw[NW - 1], K.g1);
 #pragma unroll
                     for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = zw[R - 1][v];
@@ -112,14 +165,33 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
                         for (int v = 0; v < 5; ++v) zw[c][v] = zw[c + 1][v];
                 } else {
                     double u[5], wv[5];
-                    load_cons<NDIM>(A.Us, nc, cell_at(B, i, j, k), u);
+                    if constexpr (PF) {
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) u[v] = cz[v];
+                    } else {
+                        load_cons<NDIM>(A.Us, nc, cell_at(B, i, j, k), u);
+                    }
                     bad |= eos<NDIM>(u, wv, K.g1);
 #pragma unroll
                     for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = wv[v];
                 }
             }
             // x and y halo of plane k
-            for (int e = tid; e < nhalo; e += NT) {
+            if constexpr (PF) {
+#pragma unroll
+                for (int q = 0; q < NSLOT; ++q) {
+                    const int e = tid + q * NT;
+                    if (e < nhalo) {
+                        int li, lj;
+                        (void)halo_cell(e, k, li, lj);
+                        double wv[5];
+                        bad |= eos<NDIM>(chalo[q], wv, K.g1);
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) sW[v][lj][li] = wv[v];
+                    }
+                }
+            }
+            for (int e = PF ? nhalo : tid; e < nhalo; e += NT) {
                 int li, lj;
                 int64_t ci;
                 if (e < 2 * H * wy) {
@@ -240,12 +312,13 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
                     double acc = Dx * A.idx + Dy * A.idy;
                     if constexpr (NDIM == 3) acc = acc + Dz[v] * A.idz;
                     const double L = -acc;
-                    const double T = fma(dt, L, A.Us[v * nc + ci]);
+                    const double us = PF ? cus[v] : A.Us[v * nc + ci];
+                    const double T = fma(dt, L, us);
                     double out;
                     if (A.stage == 1)
                         out = T;
                     else
-                        out = fma(A.b, T, A.a * A.Un[v * nc + ci]);
+                        out = fma(A.b, T, A.a * (PF ? cun[v] : A.Un[v * nc + ci]));
                     A.Uout[v * nc + ci] = out;
                 }
             }
@@ -429,37 +502,41 @@ hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick
 // ------------------------------------------------------------- launchers
 
 template <int NDIM, int RECON, int TX, int TY, bool GATHER>
-static hipError_t launch_stage_t(const StageArgs &a, int grid, hipStream_t st)
+static hipError_t launch_stage_t(const StageArgs &a, int variant, int grid, hipStream_t st)
 {
-    k_stage<NDIM, RECON, TX, TY, GATHER><<<grid, TX * TY, 0, st>>>(a);
+    if (variant == 1)
+        k_stage<NDIM, RECON, TX, TY, GATHER, true><<<grid, TX * TY, 0, st>>>(a);
+    else
+        k_stage<NDIM, RECON, TX, TY, GATHER, false><<<grid, TX * TY, 0, st>>>(a);
     return hipGetLastError();
 }
 
 template <int NDIM, int RECON, bool GATHER>
-static hipError_t launch_stage_r(const StageArgs &a, int tile, int grid, hipStream_t st)
+static hipError_t launch_stage_r(const StageArgs &a, int tile, int variant, int grid, hipStream_t st)
 {
     switch (tile) {
-    case 0: return launch_stage_t<NDIM, RECON, 8, 8, GATHER>(a, grid, st);
-    case 1: return launch_stage_t<NDIM, RECON, 16, 8, GATHER>(a, grid, st);
-    default: return launch_stage_t<NDIM, RECON, 16, 16, GATHER>(a, grid, st);
+    case 0: return launch_stage_t<NDIM, RECON, 8, 8, GATHER>(a, variant, grid, st);
+    case 1: return launch_stage_t<NDIM, RECON, 16, 8, GATHER>(a, variant, grid, st);
+    default: return launch_stage_t<NDIM, RECON, 16, 16, GATHER>(a, variant, grid, st);
     }
 }
 
-hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, bool gather, int grid, hipStream_t st)
+hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, int variant, bool gather, int grid,
+                        hipStream_t st)
 {
     if (grid <= 0) return hipSuccess;
     if (ndim == 3) {
         if (recon == kWENO)
-            return gather ? launch_stage_r<3, kWENO, true>(a, tile, grid, st)
-                          : launch_stage_r<3, kWENO, false>(a, tile, grid, st);
-        return gather ? launch_stage_r<3, kPLM, true>(a, tile, grid, st)
-                      : launch_stage_r<3, kPLM, false>(a, tile, grid, st);
+            return gather ? launch_stage_r<3, kWENO, true>(a, tile, variant, grid, st)
+                          : launch_stage_r<3, kWENO, false>(a, tile, variant, grid, st);
+        return gather ? launch_stage_r<3, kPLM, true>(a, tile, variant, grid, st)
+                      : launch_stage_r<3, kPLM, false>(a, tile, variant, grid, st);
     }
     if (recon == kWENO)
-        return gather ? launch_stage_r<2, kWENO, true>(a, tile, grid, st)
-                      : launch_stage_r<2, kWENO, false>(a, tile, grid, st);
-    return gather ? launch_stage_r<2, kPLM, true>(a, tile, grid, st)
-                  : launch_stage_r<2, kPLM, false>(a, tile, grid, st);
+        return gather ? launch_stage_r<2, kWENO, true>(a, tile, variant, grid, st)
+                      : launch_stage_r<2, kWENO, false>(a, tile, variant, grid, st);
+    return gather ? launch_stage_r<2, kPLM, true>(a, tile, variant, grid, st)
+                  : launch_stage_r<2, kPLM, false>(a, tile, variant, grid, st);
 }
 
 template <int NDIM>

@@ -72,7 +72,8 @@ struct VjpArgs {
     const int4 *inc;            // guard positions copying this block: (block, dir, side, kind)
 };
 
-hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, bool gather, int grid, hipStream_t st);
+hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, int variant, bool gather, int grid,
+                        hipStream_t st);
 hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl, double *dt, hipStream_t st);
 hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_fill(const TeleArgs &a, int ndim, int nblk, hipStream_t st);

@@ -51,21 +51,22 @@ SMALL = [
 
 @pytest.mark.parametrize("ndim,recon,rk,n,ng,bc,NB", SMALL)
 def test_parity_small_all_tiles(ndim, recon, rk, n, ng, bc, NB):
-    """Several tiles and a ragged tail per block; every tile shape and
-    z-chunking gives the oracle's result (and the same bits as each other)."""
+    """Several tiles and a ragged tail per block; every tile shape, z-chunking
+    and kernel schedule gives the oracle's result (and the same bits as each
+    other)."""
     p = W.random_blocks(ndim, n, ng, seed=3, recon=recon, rk=rk, bc=bc, NB=NB)
     Uo, dto = _ora_run(p, 3)
     first = None
-    for tile in (0, 1, 2):
-        for zchunk in ((0, 5) if ndim == 3 else (0,)):
-            Ug, dtg = _gpu_run(p, 3, tile=tile, zchunk=zchunk)
-            assert np.array_equal(dtg, dto), (tile, zchunk, dtg, dto)
-            assert_parity(p, Ug, Uo, f"tile {tile} zchunk {zchunk}")
-            if first is None:
-                first = Ug
-            else:
-                m = W.interior_mask(p.blocks, p.ncell, ndim)
-                assert np.array_equal(first[:, m], Ug[:, m])
+    combos = [(t, z, v) for t in (0, 1, 2) for z in ((0, 5) if ndim == 3 else (0,)) for v in (0, 1)]
+    for tile, zchunk, variant in combos:
+        Ug, dtg = _gpu_run(p, 3, tile=tile, zchunk=zchunk, variant=variant)
+        assert np.array_equal(dtg, dto), (tile, zchunk, dtg, dto)
+        assert_parity(p, Ug, Uo, f"tile {tile} zchunk {zchunk} variant {variant}")
+        if first is None:
+            first = Ug
+        else:
+            m = W.interior_mask(p.blocks, p.ncell, ndim)
+            assert np.array_equal(first[:, m], Ug[:, m])
 
 
 def test_sod_full_config():
@@ -126,7 +127,8 @@ def test_turbulence_small_all_steps():
     assert_parity(p, Ug, Uo, "turb3d-64")
 
 
-@pytest.mark.parametrize("mode_kw", [dict(mode=1), dict(use_graph=0), dict(grid=37), dict(grid=256, xcd=1)])
+@pytest.mark.parametrize("mode_kw", [dict(mode=1), dict(use_graph=0), dict(grid=37), dict(grid=256, xcd=1),
+                                     dict(variant=1), dict(mode=1, variant=1)])
 def test_launch_forms_bitwise_identical(mode_kw):
     """Per-block launches, no graph, odd persistent grids and the XCD
     placement all give the persistent graph-replayed result bit for bit."""
