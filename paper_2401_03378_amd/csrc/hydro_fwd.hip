@@ -26,7 +26,7 @@
 namespace hydro {
 
 template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF>
-__global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
+__device__ __forceinline__ void stage_body(const StageArgs &A)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
     constexpr int H = R + 1;
@@ -327,6 +327,21 @@ __global__ void __launch_bounds__(TX *TY) k_stage(StageArgs A)
     if (bad) atomicAdd(A.nbad, 1ull);
 }
 
+// Entry points of the two schedules.  The plain schedule is held to two
+// waves per SIMD (its register use fits without spills; the 16x16 tile would
+// otherwise fall to one); the prefetching schedule keeps the compiler's choice.
+template <int NDIM, int RECON, int TX, int TY, bool GATHER>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))) k_stage(StageArgs A)
+{
+    stage_body<NDIM, RECON, TX, TY, GATHER, false>(A);
+}
+
+template <int NDIM, int RECON, int TX, int TY, bool GATHER>
+__global__ void __launch_bounds__(TX *TY) k_stage_pf(StageArgs A)
+{
+    stage_body<NDIM, RECON, TX, TY, GATHER, true>(A);
+}
+
 // Per-workgroup maximum of the unsplit wave-speed sum over the interior
 // cells of its work items.
 template <int NDIM, int TX, int TY>
@@ -505,9 +520,9 @@ template <int NDIM, int RECON, int TX, int TY, bool GATHER>
 static hipError_t launch_stage_t(const StageArgs &a, int variant, int grid, hipStream_t st)
 {
     if (variant == 1)
-        k_stage<NDIM, RECON, TX, TY, GATHER, true><<<grid, TX * TY, 0, st>>>(a);
+        k_stage_pf<NDIM, RECON, TX, TY, GATHER><<<grid, TX * TY, 0, st>>>(a);
     else
-        k_stage<NDIM, RECON, TX, TY, GATHER, false><<<grid, TX * TY, 0, st>>>(a);
+        k_stage<NDIM, RECON, TX, TY, GATHER><<<grid, TX * TY, 0, st>>>(a);
     return hipGetLastError();
 }
 
