@@ -45,13 +45,14 @@ struct hydro_ctx {
     const double *g_dt = nullptr;
     int g_cdt = -1;
     // adjoint: line work lists per direction, 8x8 cell tiles, inverse links, scratch
-    WorkItem *d_lines = nullptr;  // lines of every direction (cost field = direction)
+    WorkItem *d_lines = nullptr;  // lines of every direction (cost field = direction | segment << 4)
     int nlines = 0;
+    int nseg = 1;                 // segments per line
     WorkItem *d_citems = nullptr;
     int ncitems = 0;
     int *d_inc_start = nullptr;
     int4 *d_inc = nullptr;
-    double *d_vjp = nullptr;     // gW_x | gW_y [| gW_z] | gA | gB, each nvar x ncell
+    double *d_vjp = nullptr;     // gW per direction and segment | gA | gB, each nvar x ncell
     // telescoping: thick block copies, per-stage virtual (extended) blocks and work lists
     int tele_ready = 0;
     int ngt = 0;
@@ -383,8 +384,18 @@ int setup_vjp(hydro_ctx *c)
 {
     if (c->d_vjp) return HYDRO_OK;
     const int nd = c->prm.ndim;
-    // lines along each direction, grouped by 64 within a block
+    // lines along each direction, grouped by 64 within a block; small
+    // problems cut each line into up to 4 segments for more threads
+    int64_t total_lines = 0;
+    for (int b = 0; b < c->nblocks; ++b)
+        for (int d = 0; d < nd; ++d) {
+            const hydro_block_t &B = c->hb[b];
+            total_lines += (int64_t)((d == 0) ? B.ny : B.nx) * ((nd == 3) ? ((d == 2) ? B.ny : B.nz) : 1);
+        }
+    const int64_t want = 131072;  // about two waves per SIMD
+    c->nseg = (int)std::max<int64_t>(1, std::min<int64_t>(4, (want + total_lines - 1) / std::max<int64_t>(1, total_lines)));
     std::vector<WorkItem> v;
+    for (int s = 0; s < c->nseg; ++s)
     for (int d = 0; d < nd; ++d) {
         for (int b = 0; b < c->nblocks; ++b) {
             const hydro_block_t &B = c->hb[b];
@@ -396,7 +407,7 @@ int setup_vjp(hydro_ctx *c)
                 w.block = b;
                 w.xy = l0;
                 w.z = std::min(64, nl - l0);
-                w.cost = d;
+                w.cost = d | (s << 4);
                 v.push_back(w);
             }
         }
@@ -446,7 +457,7 @@ int setup_vjp(hydro_ctx *c)
     if (!flat.empty())
         HIP_TRY(c, hipMemcpy(c->d_inc, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice));
     const size_t per = (size_t)c->nv * (size_t)std::max<int64_t>(1, c->ncell);
-    if (hipMalloc(&c->d_vjp, sizeof(double) * per * (size_t)(nd + 2)) != hipSuccess) {
+    if (hipMalloc(&c->d_vjp, sizeof(double) * per * (size_t)(nd * c->nseg + 2)) != hipSuccess) {
         c->d_vjp = nullptr;
         return fail(c, HYDRO_ENOMEM, "adjoint scratch");
     }
@@ -800,7 +811,8 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         if (e != hipSuccess) return hip_fail(c, e, "stage launch");
     }
     HIP_TRY(c, hipMemsetAsync(gUn, 0, sizeof(double) * per, st));
-    double *gW = c->d_vjp, *gbuf[2] = {c->d_vjp + nd * per, c->d_vjp + (nd + 1) * per};
+    const size_t narr = (size_t)nd * c->nseg;
+    double *gW = c->d_vjp, *gbuf[2] = {c->d_vjp + narr * per, c->d_vjp + (narr + 1) * per};
     const double *g = gUnext;
     for (int s = S, q = 0; s >= 1; --s, q ^= 1) {
         VjpArgs v{};
@@ -824,6 +836,7 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         v.gUn = (s >= 2) ? gUn : nullptr;
         v.inc_start = c->d_inc_start;
         v.inc = c->d_inc;
+        v.nseg = c->nseg;
         v.items = c->d_lines;
         v.nitems = c->nlines;
         hipError_t el = launch_vjp_lines(v, nd, c->prm.recon, 0, c->nlines, st);

@@ -131,6 +131,14 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
             const int k = z0 + kk;
             double Dz[5];
             double cus[5], cun[5], chalo[NSLOT][5], cz[5];
+            if constexpr (!PF) {
+                // operands of the RK update: issued now, consumed after the plane's work
+                if (own) {
+                    const int64_t ci = cell_at(B, i, j, k);
+                    load_cons<NDIM>(A.Us, nc, ci, cus);
+                    if (A.stage != 1) load_cons<NDIM>(A.Un, nc, ci, cun);
+                }
+            }
             if constexpr (PF) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) { cus[v] = pus[v]; cun[v] = pun[v]; cz[v] = pz[v]; }
@@ -312,13 +320,12 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                     double acc = Dx * A.idx + Dy * A.idy;
                     if constexpr (NDIM == 3) acc = acc + Dz[v] * A.idz;
                     const double L = -acc;
-                    const double us = PF ? cus[v] : A.Us[v * nc + ci];
-                    const double T = fma(dt, L, us);
+                    const double T = fma(dt, L, cus[v]);
                     double out;
                     if (A.stage == 1)
                         out = T;
                     else
-                        out = fma(A.b, T, A.a * (PF ? cun[v] : A.Un[v * nc + ci]));
+                        out = fma(A.b, T, A.a * cun[v]);
                     A.Uout[v * nc + ci] = out;
                 }
             }

@@ -70,6 +70,7 @@ struct VjpArgs {
     double *gUn;                // += a gOut (null: skip)
     const int *inc_start;       // per block: range in inc
     const int4 *inc;            // guard positions copying this block: (block, dir, side, kind)
+    int32_t nseg;               // requested segments per line (arrays per direction)
 };
 
 hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, int variant, bool gather, int grid,

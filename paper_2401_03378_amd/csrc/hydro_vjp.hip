@@ -5,16 +5,18 @@
 //
 // A stage is U_{s+1} = b (U_s + dt L(U_s)) + a U^n with
 // L = -sum_d (F_{d,i+1/2} - F_{d,i-1/2})/dx_d.  Its transpose splits into
-//  k_vjp_lines     one thread per 1D line of a block (every direction in one
-//                  launch), streaming along the line: it recomputes
+//  k_vjp_lines     one thread per 1D line (or segment of a line, on small
+//                  problems) of a block, every direction in one launch,
+//                  streaming along it: it recomputes
 //                  primitives, reconstruction (with fallback) and the HLLC
 //                  branch, then reverses face flux -> face states -> stencil
 //                  primitives, and writes the primitive cotangent of every
 //                  position the line's stencils read (interior and guard
 //                  positions) into a padded array of its own direction, so no
 //                  two threads write one element.
-//  k_vjp_cells     one thread per interior cell: sums the directions' arrays
-//                  in the order x, y, z, adds the cotangents of the
+//  k_vjp_cells     one thread per interior cell: sums the arrays of the
+//                  directions and line segments that cover it in a fixed
+//                  order (x, y, z; segments in order), adds the cotangents of the
 //                  guard positions that are copies of the cell (through the
 //                  inverse link table; neighbour, periodic and outflow
 //                  copies), applies the EOS transpose and forms
@@ -27,9 +29,22 @@ namespace hydro {
 
 // ------------------------------------------------------- point-wise VJPs
 
+// Reverse of the wave-speed part of a face state: c = sqrt(gamma p r),
+// r = 1/rho, given cotangents gc and gr.
+__device__ __forceinline__ void wave_vjp(const double (&w)[5], double gc, double gr, double (&gW)[5], const Consts &K)
+{
+    const double rho = w[0], p = w[4];
+    const double r = 1.0 / rho, c = sqrt((K.gamma * p) * r);
+    const double gx = gc / (2.0 * c);
+    gW[4] += gx * K.gamma * r;
+    const double grt = gr + gx * K.gamma * p;
+    gW[0] += -r * r * grt;
+}
+
+// Reverse of U and F of a face state (state_flux without c and r).
 template <int NDIM, int N>
-__device__ __forceinline__ void state_flux_vjp(const double (&w)[5], const double (&gU)[5], const double (&gF)[5],
-                                               double gc, double gr, double (&gW)[5], const Consts &K)
+__device__ __forceinline__ void cons_flux_vjp(const double (&w)[5], const double (&gU)[5], const double (&gF)[5],
+                                              double (&gW)[5], const Consts &K)
 {
     constexpr int NV = NDIM + 2;
     const double rho = w[0], p = w[4], un = w[1 + N];
@@ -64,11 +79,6 @@ __device__ __forceinline__ void state_flux_vjp(const double (&w)[5], const doubl
     grho += gE * 0.5 * u2;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) gu[d] += gE * rho * w[1 + d];
-    const double r = 1.0 / rho, c = sqrt((K.gamma * p) * r);
-    const double gx = gc / (2.0 * c);
-    gp += gx * K.gamma * r;
-    const double grt = gr + gx * K.gamma * p;
-    grho += -r * r * grt;
     gW[0] += grho;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) gW[1 + d] += gu[d];
@@ -76,106 +86,123 @@ __device__ __forceinline__ void state_flux_vjp(const double (&w)[5], const doubl
 }
 
 // Reverse of the HLLC flux: recomputes the forward face solution (region and
-// Davis arguments included) and accumulates gWL, gWR.
+// Davis arguments included) and accumulates gWL, gWR.  Only the side whose
+// U and F enter the flux has them formed and transposed; the other side
+// contributes through its wave speed, pressure, density and normal velocity.
 template <int NDIM, int N>
 __device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&WR)[5], const double (&gF)[5],
                                          double (&gWL)[5], double (&gWR)[5], const Consts &K)
 {
     constexpr int NV = NDIM + 2;
-    double UL[5], UR[5], FL[5], FR[5], rL, rR, cL, cR;
-    state_flux<NDIM, N>(WL, UL, FL, rL, cL, K);
-    state_flux<NDIM, N>(WR, UR, FR, rR, cR, K);
+    const double rL = 1.0 / WL[0], cL = sqrt((K.gamma * WL[4]) * rL);
+    const double rR = 1.0 / WR[0], cR = sqrt((K.gamma * WR[4]) * rR);
     const double uL = WL[1 + N], uR = WR[1 + N];
     const double sl0 = uL - cL, sl1 = uR - cR, sr0 = uL + cL, sr1 = uR + cR;
-    const bool slR = !(sl0 <= sl1);   // S_L from the right state
-    const bool srR = !(sr0 >= sr1);   // S_R from the right state
+    if (sl0 <= sl1 ? sl0 >= 0.0 : sl1 >= 0.0) {           // F = F_L
+        const double zero[5] = {0, 0, 0, 0, 0};
+        cons_flux_vjp<NDIM, N>(WL, zero, gF, gWL, K);
+        return;
+    }
+    const bool slR = !(sl0 <= sl1);
+    const bool srR = !(sr0 >= sr1);
     const double SL = slR ? sl1 : sl0, SR = srR ? sr1 : sr0;
     const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
     const double Num = (WR[4] - WL[4]) + (mL * uL - mR * uR), Den = mL - mR;
     const double Ss = Num / Den;
-    double gUL[5] = {0, 0, 0, 0, 0}, gUR[5] = {0, 0, 0, 0, 0}, gFL[5] = {0, 0, 0, 0, 0}, gFR[5] = {0, 0, 0, 0, 0};
-    double gcL = 0.0, gcR = 0.0, grL = 0.0, grR = 0.0;
-    if (SL >= 0.0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) gFL[v] = gF[v];
-    } else if (Ss >= 0.0 || SR > 0.0) {
-        const bool right = !(Ss >= 0.0);
-        const double(&W)[5] = right ? WR : WL;
-        const double(&UK)[5] = right ? UR : UL;
-        const double SK = right ? SR : SL, mK = right ? mR : mL, rK = right ? rR : rL;
-        const double uK = W[1 + N];
-        const double den = SK - Ss, chi = mK / den;
-        const double q = W[4] / mK;
-        const double Bq = UK[NV - 1] * rK + (Ss - uK) * (Ss + q);
-        double Us[5];
-        Us[0] = chi;
-#pragma unroll
-        for (int d = 0; d < NDIM; ++d) Us[1 + d] = (d == N) ? chi * Ss : chi * W[1 + d];
-        Us[NV - 1] = chi * Bq;
-        double gSK = 0.0, gUs[5], gUK[5];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            gSK += gF[v] * (Us[v] - UK[v]);
-            gUs[v] = SK * gF[v];
-            gUK[v] = -(SK * gF[v]);
-        }
-        double gWK[5] = {0, 0, 0, 0, 0};
-        double gchi = gUs[0] + gUs[1 + N] * Ss + gUs[NV - 1] * Bq;
-#pragma unroll
-        for (int d = 0; d < NDIM; ++d)
-            if (d != N) {
-                gchi += gUs[1 + d] * W[1 + d];
-                gWK[1 + d] += gUs[1 + d] * chi;
-            }
-        double gSs = gUs[1 + N] * chi;
-        const double gB = gUs[NV - 1] * chi;
-        gUK[NV - 1] += gB * rK;
-        const double grK = gB * UK[NV - 1];
-        gSs += gB * (Ss + q) + gB * (Ss - uK);
-        gWK[1 + N] -= gB * (Ss + q);
-        const double gq = gB * (Ss - uK);
-        gWK[4] += gq / mK;
-        double gmK = -gq * q / mK;
-        gmK += gchi / den;
-        const double gden = -gchi * chi / den;
-        gSK += gden;
-        gSs -= gden;
-        double gSL = 0.0, gSR = 0.0, gmL = 0.0, gmR = 0.0;
-        if (right) {
-            gSR += gSK; gmR += gmK; grR += grK;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) { gFR[v] = gF[v]; gUR[v] = gUK[v]; }
-#pragma unroll
-            for (int v = 0; v < 5; ++v) gWR[v] += gWK[v];
-        } else {
-            gSL += gSK; gmL += gmK; grL += grK;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) { gFL[v] = gF[v]; gUL[v] = gUK[v]; }
-#pragma unroll
-            for (int v = 0; v < 5; ++v) gWL[v] += gWK[v];
-        }
-        const double gN = gSs / Den, gD = -gSs * Ss / Den;
-        gWR[4] += gN;
-        gWL[4] -= gN;
-        gmL += gN * uL + gD;
-        gmR += -gN * uR - gD;
-        double guL = gN * mL, guR = -gN * mR;
-        gWL[0] += gmL * (SL - uL);
-        gSL += gmL * WL[0];
-        guL -= gmL * WL[0];
-        gWR[0] += gmR * (SR - uR);
-        gSR += gmR * WR[0];
-        guR -= gmR * WR[0];
-        if (slR) { guR += gSL; gcR -= gSL; } else { guL += gSL; gcL -= gSL; }
-        if (srR) { guR += gSR; gcR += gSR; } else { guL += gSR; gcL += gSR; }
-        gWL[1 + N] += guL;
-        gWR[1 + N] += guR;
-    } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) gFR[v] = gF[v];
+    if (!(Ss >= 0.0 || SR > 0.0)) {                       // F = F_R
+        const double zero[5] = {0, 0, 0, 0, 0};
+        cons_flux_vjp<NDIM, N>(WR, zero, gF, gWR, K);
+        return;
     }
-    state_flux_vjp<NDIM, N>(WL, gUL, gFL, gcL, grL, gWL, K);
-    state_flux_vjp<NDIM, N>(WR, gUR, gFR, gcR, grR, gWR, K);
+    double gcL = 0.0, gcR = 0.0, grL = 0.0, grR = 0.0;
+    const bool right = !(Ss >= 0.0);
+    const double(&W)[5] = right ? WR : WL;
+    double UK[5], FK[5];
+    {
+        const double rho = W[0], p = W[4], un = W[1 + N];
+        double ke;
+        if constexpr (NDIM == 3)
+            ke = 0.5 * (rho * ((W[1] * W[1] + W[2] * W[2]) + W[3] * W[3]));
+        else
+            ke = 0.5 * (rho * (W[1] * W[1] + W[2] * W[2]));
+        const double E = p * K.ig1 + ke;
+        UK[0] = rho;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) UK[1 + d] = rho * W[1 + d];
+        UK[NV - 1] = E;
+        const double fr = rho * un;
+        FK[0] = fr;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) FK[1 + d] = (d == N) ? (fr * un) + p : fr * W[1 + d];
+        FK[NV - 1] = (E + p) * un;
+    }
+    const double SK = right ? SR : SL, mK = right ? mR : mL, rK = right ? rR : rL;
+    const double uK = W[1 + N];
+    const double den = SK - Ss, chi = mK / den;
+    const double q = W[4] / mK;
+    const double Bq = UK[NV - 1] * rK + (Ss - uK) * (Ss + q);
+    double Us[5];
+    Us[0] = chi;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) Us[1 + d] = (d == N) ? chi * Ss : chi * W[1 + d];
+    Us[NV - 1] = chi * Bq;
+    double gSK = 0.0, gUs[5], gUK[5];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        gSK += gF[v] * (Us[v] - UK[v]);
+        gUs[v] = SK * gF[v];
+        gUK[v] = -(SK * gF[v]);
+    }
+    double gWK[5] = {0, 0, 0, 0, 0};
+    double gchi = gUs[0] + gUs[1 + N] * Ss + gUs[NV - 1] * Bq;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d)
+        if (d != N) {
+            gchi += gUs[1 + d] * W[1 + d];
+            gWK[1 + d] += gUs[1 + d] * chi;
+        }
+    double gSs = gUs[1 + N] * chi;
+    const double gB = gUs[NV - 1] * chi;
+    gUK[NV - 1] += gB * rK;
+    const double grK = gB * UK[NV - 1];
+    gSs += gB * (Ss + q) + gB * (Ss - uK);
+    gWK[1 + N] -= gB * (Ss + q);
+    const double gq = gB * (Ss - uK);
+    gWK[4] += gq / mK;
+    double gmK = -gq * q / mK;
+    gmK += gchi / den;
+    const double gden = -gchi * chi / den;
+    gSK += gden;
+    gSs -= gden;
+    cons_flux_vjp<NDIM, N>(W, gUK, gF, gWK, K);          // F_K + terms through U_K
+    double gSL = 0.0, gSR = 0.0, gmL = 0.0, gmR = 0.0;
+    if (right) {
+        gSR += gSK; gmR += gmK; grR += grK;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gWR[v] += gWK[v];
+    } else {
+        gSL += gSK; gmL += gmK; grL += grK;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gWL[v] += gWK[v];
+    }
+    const double gN = gSs / Den, gD = -gSs * Ss / Den;
+    gWR[4] += gN;
+    gWL[4] -= gN;
+    gmL += gN * uL + gD;
+    gmR += -gN * uR - gD;
+    double guL = gN * mL, guR = -gN * mR;
+    gWL[0] += gmL * (SL - uL);
+    gSL += gmL * WL[0];
+    guL -= gmL * WL[0];
+    gWR[0] += gmR * (SR - uR);
+    gSR += gmR * WR[0];
+    guR -= gmR * WR[0];
+    if (slR) { guR += gSL; gcR -= gSL; } else { guL += gSL; gcL -= gSL; }
+    if (srR) { guR += gSR; gcR += gSR; } else { guL += gSR; gcL += gSR; }
+    gWL[1 + N] += guL;
+    gWR[1 + N] += guR;
+    wave_vjp(WL, gcL, grL, gWL, K);
+    wave_vjp(WR, gcR, grR, gWR, K);
 }
 
 // Reverse of the limited linear slope of (qa, q0, qb): adds to g[0..2].
@@ -295,6 +322,25 @@ __device__ __forceinline__ void recon_cell_vjp(const double (&s)[S][5], bool fb,
 template <int NDIM>
 __device__ __forceinline__ int wslot(int v) { return v == 4 ? NDIM + 1 : v; }
 
+// Segments of a line: a line of n cells (faces 0..n) is cut into k segments
+// of L = ceil(n/k) faces; segment s owns faces [f0, f1] and writes the
+// cotangents of positions [f0-1-R, f1+R] into its own array.  k is the
+// requested count, reduced so every segment spans at least 2R+1 cells.
+template <int R>
+__device__ __forceinline__ int seg_count(int n, int nseg)
+{
+    const int cap = n / (2 * R + 1);
+    return max(1, min(nseg, cap));
+}
+
+template <int R>
+__device__ __forceinline__ void seg_range(int n, int k, int s, int &f0, int &f1)
+{
+    const int L = (n + k - 1) / k;
+    f0 = (s == 0) ? 0 : s * L + 1;
+    f1 = min((s + 1) * L, n);
+}
+
 // ------------------------------------------------------------ line kernel
 
 template <int D>
@@ -315,6 +361,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
     constexpr int NWIN = 2 * R + 2;   // primitives at positions t-2R-1 .. t
     const int nl = it.z;               // lines in this item
     if (lane >= nl) return;
+    const int seg = it.cost >> 4;
     const DevBlock B = A.blocks[it.block];
     const FaceSrc *F6 = A.faces + 6 * (int64_t)it.block;
     const int L = it.xy + lane;
@@ -325,6 +372,11 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
     const Consts K{A.gamma, A.g1, A.ig1};
     const double dt = *A.dt;
     const double id = (D == 0) ? A.idx : ((D == 1) ? A.idy : A.idz);
+    const int kseg = seg_count<R>(n, A.nseg);
+    if (seg >= kseg) return;
+    int f0, f1;
+    seg_range<R>(n, kseg, seg, f0, f1);
+    if (f0 > f1) return;
 
     double Wwin[NWIN][5];
     double gWwin[NS][5];
@@ -340,8 +392,18 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
         for (int v = 0; v < 5; ++v) gWwin[c][v] = 0.0;
 #pragma unroll
     for (int v = 0; v < 5; ++v) { qp_prev[v] = 0.0; gqm_prev[v] = 0.0; gD_prev[v] = 0.0; }
+    if (f0 >= 1) {        // flux difference of the cell left of the first face
+        int i, j, k;
+        line_coords<D>(f0 - 1, e1, e2, i, j, k);
+        const int64_t ci = cell_at(B, i, j, k);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double gT = A.b * A.gOut[v * nc + ci];
+            gD_prev[v] = -(dt * gT) * id;
+        }
+    }
 
-    double *gWd = A.gW + (int64_t)D * NV * nc;      // this direction's array
+    double *gWd = A.gW + ((int64_t)D * A.nseg + seg) * NV * nc;   // this direction's and segment's array
     auto emit = [&](int p, const double (&gw)[5]) {
         int i, j, k;
         line_coords<D>(p, e1, e2, i, j, k);
@@ -353,7 +415,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
         }
     };
 
-    for (int t = -H; t < n + H; ++t) {
+    for (int t = f0 - H; t <= f1 + R; ++t) {
         // primitives at the new position
 #pragma unroll
         for (int c = 0; c < NWIN - 1; ++c)
@@ -367,7 +429,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
             eos<NDIM>(u, Wwin[NWIN - 1], K.g1);
         }
         const int c = t - R;          // reconstruction cell completed by this position
-        if (c >= -1) {
+        if (c >= f0 - 1) {
             double s[NS][5], qm[5], qp[5];
 #pragma unroll
             for (int q = 0; q < NS; ++q)
@@ -375,7 +437,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
                 for (int v = 0; v < 5; ++v) s[q][v] = Wwin[q + 1][v];
             const bool fb = recon_cell<NDIM, RECON>(s, qm, qp);
             double gqp_c1[5] = {0, 0, 0, 0, 0}, gqm_c[5] = {0, 0, 0, 0, 0};
-            if (c >= 0) {
+            if (c >= f0) {
                 // cotangent of face c-1/2: gD_{c-1} - gD_c
                 double gD[5] = {0, 0, 0, 0, 0};
                 if (c < n) {
@@ -412,7 +474,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
         }
         // position t-2R-1 receives nothing more
         const int pout = t - 2 * R - 1;
-        if (pout >= -H) emit(pout, gWwin[0]);
+        if (pout >= f0 - H) emit(pout, gWwin[0]);
 #pragma unroll
         for (int q = 0; q < NS - 1; ++q)
 #pragma unroll
@@ -420,7 +482,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
 #pragma unroll
         for (int v = 0; v < 5; ++v) gWwin[NS - 1][v] = 0.0;
     }
-    // last reconstruction cell (n): no face on its right in this block
+    // last reconstruction cell (f1): its right face is not this segment's
     {
         double s1[NS][5], g1[NS][5];
         const double zero[5] = {0, 0, 0, 0, 0};
@@ -433,18 +495,20 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
         for (int q = 0; q < NS; ++q) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) gWwin[q][v] += g1[q][v];
-            emit(n - R + q, gWwin[q]);
+            emit(f1 - R + q, gWwin[q]);
         }
     }
 }
 
-// One launch for every direction: work item cost field = direction.
+// One launch for every direction and segment: work item cost field =
+// direction | segment << 4.
 template <int NDIM, int RECON>
 __global__ void __launch_bounds__(64) k_vjp_lines(VjpArgs A)
 {
     const WorkItem it = A.items[blockIdx.x];
-    if (it.cost == 0) vjp_line<NDIM, RECON, 0>(A, it, threadIdx.x);
-    else if (it.cost == 1) vjp_line<NDIM, RECON, 1>(A, it, threadIdx.x);
+    const int dir = it.cost & 15;
+    if (dir == 0) vjp_line<NDIM, RECON, 0>(A, it, threadIdx.x);
+    else if (dir == 1) vjp_line<NDIM, RECON, 1>(A, it, threadIdx.x);
     else if constexpr (NDIM == 3) vjp_line<NDIM, RECON, 2>(A, it, threadIdx.x);
 }
 
@@ -474,8 +538,23 @@ template <int NDIM, int H, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
 {
     constexpr int NV = NDIM + 2;
+    constexpr int R = H - 1;
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     const int64_t nc = A.nc;
+    const int64_t astride = (int64_t)NV * nc;
+    // sum of the segment arrays of direction d whose ranges contain position p
+    auto seg_sum = [&](const DevBlock &X, int d, int p, int64_t cell, double (&gw)[5]) {
+        const int n = (d == 0) ? X.nx : ((d == 1) ? X.ny : X.nz);
+        const int k = seg_count<R>(n, A.nseg);
+        for (int s = 0; s < k; ++s) {
+            int f0, f1;
+            seg_range<R>(n, k, s, f0, f1);
+            if (f0 > f1 || p < f0 - 1 - R || p > f1 + R) continue;
+            const double *g = A.gW + ((int64_t)d * A.nseg + s) * astride;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] += g[v * nc + cell];
+        }
+    };
     for (int w = blockIdx.x; w < A.ncitems; w += gridDim.x) {
         const WorkItem it = A.citems[w];
         const DevBlock B = A.blocks[it.block];
@@ -489,13 +568,9 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
             double gw[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) gw[v] = 0.0;
-            const int64_t dstride = (int64_t)NV * nc;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                double t = A.gW[v * nc + ci] + A.gW[dstride + v * nc + ci];
-                if constexpr (NDIM == 3) t = t + A.gW[2 * dstride + v * nc + ci];
-                gw[v == NDIM + 1 ? 4 : v] = t;
-            }
+            seg_sum(B, 0, i, ci, gw);
+            seg_sum(B, 1, j, ci, gw);
+            if constexpr (NDIM == 3) seg_sum(B, 2, k, ci, gw);
             // guard positions (of this or other blocks) that copy this cell
             for (int e = inc0; e < inc1; ++e) {
                 const int4 q = A.inc[e];                 // x = block, y = dir, z = side, w = kind
@@ -515,9 +590,7 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
                 for (int l = lo; l <= hi; ++l) {
                     const int gpos = gp0 + step * l;
                     const int gi = (d == 0) ? gpos : i, gj = (d == 1) ? gpos : j, gk = (d == 2) ? gpos : k;
-                    const int64_t gc = cell_at(X, gi, gj, gk);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] += A.gW[d * dstride + v * nc + gc];
+                    seg_sum(X, d, gpos, cell_at(X, gi, gj, gk), gw);
                 }
             }
             double u[5], gu[5];
