@@ -342,14 +342,16 @@ static void weno5_vjp(const double *q, double gqm, double gqp, double *g)
 {
     const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
     double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
-    double t[3], w[3], be[3], o[3];
+    double t[3], w[3], be[3], s[3], o[3];
     t[0] = (a - 2.0 * b) + c;  w[0] = (a - 4.0 * b) + 3.0 * c;
     t[1] = (b - 2.0 * c) + d;  w[1] = b - d;
     t[2] = (c - 2.0 * d) + e;  w[2] = (3.0 * c - 4.0 * d) + e;
     for (int k = 0; k < 3; k++) {
         be[k] = k13 * (t[k] * t[k]) + 0.25 * (w[k] * w[k]);
-        o[k] = 1.0 / ((eps + be[k]) * (eps + be[k]));
+        s[k] = (eps + be[k]) * (eps + be[k]);
     }
+    /* unnormalised weights as in the forward: o_k = product of the other s_j */
+    o[0] = s[1] * s[2];  o[1] = s[0] * s[2];  o[2] = s[0] * s[1];
     double go[3] = {0.0, 0.0, 0.0};
     /* right face */
     {
@@ -358,13 +360,14 @@ static void weno5_vjp(const double *q, double gqm, double gqp, double *g)
         p[1] = ((-b + 5.0 * c) + 2.0 * d) * k6;
         p[2] = ((2.0 * c + 5.0 * d) - e) * k6;
         al[0] = 0.1 * o[0];  al[1] = 0.6 * o[1];  al[2] = 0.3 * o[2];
-        double S = (al[0] + al[1]) + al[2];
-        double qv = ((al[0] * p[0] + al[1] * p[1]) + al[2] * p[2]) / S;
+        double iS = 1.0 / ((al[0] + al[1]) + al[2]);
+        double gS = gqp * iS;
+        double qv = ((al[0] * p[0] + al[1] * p[1]) + al[2] * p[2]) * iS;
         double gp[3];
-        for (int k = 0; k < 3; k++) gp[k] = gqp * al[k] / S;
-        go[0] += 0.1 * gqp * (p[0] - qv) / S;
-        go[1] += 0.6 * gqp * (p[1] - qv) / S;
-        go[2] += 0.3 * gqp * (p[2] - qv) / S;
+        for (int k = 0; k < 3; k++) gp[k] = gS * al[k];
+        go[0] += 0.1 * gS * (p[0] - qv);
+        go[1] += 0.6 * gS * (p[1] - qv);
+        go[2] += 0.3 * gS * (p[2] - qv);
         g[0] += k6 * (2.0 * gp[0]);
         g[1] += k6 * (-7.0 * gp[0] - gp[1]);
         g[2] += k6 * (11.0 * gp[0] + 5.0 * gp[1] + 2.0 * gp[2]);
@@ -378,23 +381,29 @@ static void weno5_vjp(const double *q, double gqm, double gqp, double *g)
         p[1] = ((-d + 5.0 * c) + 2.0 * b) * k6;
         p[2] = ((2.0 * c + 5.0 * b) - a) * k6;
         al[0] = 0.1 * o[2];  al[1] = 0.6 * o[1];  al[2] = 0.3 * o[0];
-        double S = (al[0] + al[1]) + al[2];
-        double qv = ((al[0] * p[0] + al[1] * p[1]) + al[2] * p[2]) / S;
+        double iS = 1.0 / ((al[0] + al[1]) + al[2]);
+        double gS = gqm * iS;
+        double qv = ((al[0] * p[0] + al[1] * p[1]) + al[2] * p[2]) * iS;
         double gp[3];
-        for (int k = 0; k < 3; k++) gp[k] = gqm * al[k] / S;
-        go[2] += 0.1 * gqm * (p[0] - qv) / S;
-        go[1] += 0.6 * gqm * (p[1] - qv) / S;
-        go[0] += 0.3 * gqm * (p[2] - qv) / S;
+        for (int k = 0; k < 3; k++) gp[k] = gS * al[k];
+        go[2] += 0.1 * gS * (p[0] - qv);
+        go[1] += 0.6 * gS * (p[1] - qv);
+        go[0] += 0.3 * gS * (p[2] - qv);
         g[4] += k6 * (2.0 * gp[0]);
         g[3] += k6 * (-7.0 * gp[0] - gp[1]);
         g[2] += k6 * (11.0 * gp[0] + 5.0 * gp[1] + 2.0 * gp[2]);
         g[1] += k6 * (2.0 * gp[1] + 5.0 * gp[2]);
         g[0] += k6 * (-gp[2]);
     }
-    /* o_k = (eps + beta_k)^-2 ; beta_k = k13 t_k^2 + w_k^2 / 4 */
+    /* o_0 = s_1 s_2, o_1 = s_0 s_2, o_2 = s_0 s_1; s_k = (eps + beta_k)^2;
+     * beta_k = k13 t_k^2 + w_k^2 / 4 */
+    double gs[3];
+    gs[0] = go[1] * s[2] + go[2] * s[1];
+    gs[1] = go[0] * s[2] + go[2] * s[0];
+    gs[2] = go[0] * s[1] + go[1] * s[0];
     double gt[3], gw[3];
     for (int k = 0; k < 3; k++) {
-        double gbe = -2.0 * go[k] * o[k] / (eps + be[k]);
+        double gbe = 2.0 * (eps + be[k]) * gs[k];
         gt[k] = 2.0 * k13 * t[k] * gbe;
         gw[k] = 0.5 * w[k] * gbe;
     }

@@ -149,6 +149,33 @@ def test_weno5_order_and_linear_weights():
     assert np.max(np.abs(qp - lin)) < 1e-9
 
 
+def test_weno5_matches_normalised_weight_form():
+    """The oracle takes the nonlinear weights as d_k times the product of the
+    two other (eps + beta_k)^2; the Jiang-Shu form normalises
+    alpha_k = d_k / (eps + beta_k)^2.  Both give the same face values (to
+    rounding) on smooth data, discontinuities and jumps of eight decades."""
+    rng = np.random.default_rng(11)
+    smooth = rng.standard_normal((300, 5)) * 1e-3 + np.linspace(0, 1e-3, 5)
+    steps = np.where(rng.random((300, 5)) < 0.5, 1.0, 0.0) * 10.0 ** rng.uniform(-4, 4, (300, 1))
+    mixed = rng.standard_normal((300, 5)) * 10.0 ** rng.uniform(-6, 5, (300, 5))
+    q = np.concatenate([smooth, steps + 1.0, mixed])
+    qm, qp = O.weno5(q)
+    a, b, c, d, e = q.T
+    beta = np.stack([
+        13.0 / 12.0 * (a - 2 * b + c) ** 2 + 0.25 * (a - 4 * b + 3 * c) ** 2,
+        13.0 / 12.0 * (b - 2 * c + d) ** 2 + 0.25 * (b - d) ** 2,
+        13.0 / 12.0 * (c - 2 * d + e) ** 2 + 0.25 * (3 * c - 4 * d + e) ** 2])
+    alpha = np.array([0.1, 0.6, 0.3])[:, None] / (1e-6 + beta) ** 2
+    wr = alpha / alpha.sum(axis=0)
+    right = np.stack([(2 * a - 7 * b + 11 * c) / 6, (-b + 5 * c + 2 * d) / 6, (2 * c + 5 * d - e) / 6])
+    alpha_l = np.array([0.1, 0.6, 0.3])[:, None] / (1e-6 + beta[::-1]) ** 2
+    wl = alpha_l / alpha_l.sum(axis=0)
+    left = np.stack([(2 * e - 7 * d + 11 * c) / 6, (-d + 5 * c + 2 * b) / 6, (2 * c + 5 * b - a) / 6])
+    scale = np.max(np.abs(q), axis=1)
+    assert np.max(np.abs(qp - (wr * right).sum(axis=0)) / scale) < 1e-13
+    assert np.max(np.abs(qm - (wl * left).sum(axis=0)) / scale) < 1e-13
+
+
 def test_weno5_step_is_essentially_non_oscillatory():
     q = np.array([[1.0, 1.0, 1.0, 0.0, 0.0], [1.0, 1.0, 0.0, 0.0, 0.0]])
     qm, qp = O.weno5(q)
