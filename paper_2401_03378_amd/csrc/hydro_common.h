@@ -133,9 +133,12 @@ __device__ __forceinline__ void weno5(double a, double b, double c, double d, do
     t = (c - 2.0 * d) + e;
     w = (3.0 * c - 4.0 * d) + e;
     const double b2 = k13 * (t * t) + 0.25 * (w * w);
-    const double o0 = 1.0 / ((eps + b0) * (eps + b0));
-    const double o1 = 1.0 / ((eps + b1) * (eps + b1));
-    const double o2 = 1.0 / ((eps + b2) * (eps + b2));
+    // alpha_k = d_k / s_k, s_k = (eps + beta_k)^2, scaled by s_0 s_1 s_2 (the
+    // normalised weights are unchanged): no division for the weights.
+    const double s0 = (eps + b0) * (eps + b0);
+    const double s1 = (eps + b1) * (eps + b1);
+    const double s2 = (eps + b2) * (eps + b2);
+    const double o0 = s1 * s2, o1 = s0 * s2, o2 = s0 * s1;
     {
         const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * k6;
         const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;

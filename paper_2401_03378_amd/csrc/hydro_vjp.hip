@@ -227,9 +227,11 @@ __device__ __forceinline__ void plm_vjp(double qa, double q0, double qb, double 
 // Reverse of WENO5-JS on (a,b,c,d,e): adds to g[0..4].
 __device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gqp, double *g)
 {
+    // Forward: s_k = (eps + beta_k)^2, o_k = product of the two other s_j,
+    // face value = sum(d_k o_k p_k) / sum(d_k o_k).  One reciprocal per face.
     const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
     const double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
-    double t[3], w[3], be[3], o[3];
+    double t[3], w[3], sq[3], s[3];
     t[0] = (a - 2.0 * b) + c;
     w[0] = (a - 4.0 * b) + 3.0 * c;
     t[1] = (b - 2.0 * c) + d;
@@ -238,21 +240,23 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gq
     w[2] = (3.0 * c - 4.0 * d) + e;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        be[k] = k13 * (t[k] * t[k]) + 0.25 * (w[k] * w[k]);
-        o[k] = 1.0 / ((eps + be[k]) * (eps + be[k]));
+        sq[k] = eps + (k13 * (t[k] * t[k]) + 0.25 * (w[k] * w[k]));
+        s[k] = sq[k] * sq[k];
     }
+    const double o[3] = {s[1] * s[2], s[0] * s[2], s[0] * s[1]};
     double go0 = 0.0, go1 = 0.0, go2 = 0.0;
     {   // right face
         const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * k6;
         const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;
         const double p2 = ((2.0 * c + 5.0 * d) - e) * k6;
         const double a0 = 0.1 * o[0], a1 = 0.6 * o[1], a2 = 0.3 * o[2];
-        const double S = (a0 + a1) + a2;
-        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) / S;
-        const double gp0 = gqp * a0 / S, gp1 = gqp * a1 / S, gp2 = gqp * a2 / S;
-        go0 += 0.1 * gqp * (p0 - qv) / S;
-        go1 += 0.6 * gqp * (p1 - qv) / S;
-        go2 += 0.3 * gqp * (p2 - qv) / S;
+        const double iS = 1.0 / ((a0 + a1) + a2);
+        const double gS = gqp * iS;
+        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
+        const double gp0 = gS * a0, gp1 = gS * a1, gp2 = gS * a2;
+        go0 += 0.1 * gS * (p0 - qv);
+        go1 += 0.6 * gS * (p1 - qv);
+        go2 += 0.3 * gS * (p2 - qv);
         g[0] += k6 * (2.0 * gp0);
         g[1] += k6 * (-7.0 * gp0 - gp1);
         g[2] += k6 * (11.0 * gp0 + 5.0 * gp1 + 2.0 * gp2);
@@ -264,23 +268,25 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gq
         const double p1 = ((-d + 5.0 * c) + 2.0 * b) * k6;
         const double p2 = ((2.0 * c + 5.0 * b) - a) * k6;
         const double a0 = 0.1 * o[2], a1 = 0.6 * o[1], a2 = 0.3 * o[0];
-        const double S = (a0 + a1) + a2;
-        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) / S;
-        const double gp0 = gqm * a0 / S, gp1 = gqm * a1 / S, gp2 = gqm * a2 / S;
-        go2 += 0.1 * gqm * (p0 - qv) / S;
-        go1 += 0.6 * gqm * (p1 - qv) / S;
-        go0 += 0.3 * gqm * (p2 - qv) / S;
+        const double iS = 1.0 / ((a0 + a1) + a2);
+        const double gS = gqm * iS;
+        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
+        const double gp0 = gS * a0, gp1 = gS * a1, gp2 = gS * a2;
+        go2 += 0.1 * gS * (p0 - qv);
+        go1 += 0.6 * gS * (p1 - qv);
+        go0 += 0.3 * gS * (p2 - qv);
         g[4] += k6 * (2.0 * gp0);
         g[3] += k6 * (-7.0 * gp0 - gp1);
         g[2] += k6 * (11.0 * gp0 + 5.0 * gp1 + 2.0 * gp2);
         g[1] += k6 * (2.0 * gp1 + 5.0 * gp2);
         g[0] += k6 * (-gp2);
     }
-    const double go[3] = {go0, go1, go2};
+    // o_0 = s_1 s_2, o_1 = s_0 s_2, o_2 = s_0 s_1
+    const double gs[3] = {go1 * s[2] + go2 * s[1], go0 * s[2] + go2 * s[0], go0 * s[1] + go1 * s[0]};
     double gt[3], gw[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double gbe = -2.0 * go[k] * o[k] / (eps + be[k]);
+        const double gbe = 2.0 * sq[k] * gs[k];
         gt[k] = 2.0 * k13 * t[k] * gbe;
         gw[k] = 0.5 * w[k] * gbe;
     }
