@@ -120,38 +120,41 @@ __device__ __forceinline__ void plm(double qa, double q0, double qb, double &qm,
 }
 
 // WENO5-JS on (a,b,c,d,e) = q_{i-2..i+2}; both faces share beta_k.
+// Candidates and indicators are evaluated with fused multiply-adds in the
+// order written; the weights are alpha_k = d_k / s_k, s_k = (eps + beta_k)^2,
+// scaled by s_0 s_1 s_2 (the normalised weights are unchanged), so the only
+// divisions are one per face.
 __device__ __forceinline__ void weno5(double a, double b, double c, double d, double e, double &qm, double &qp)
 {
-    const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
+    const double k13 = 13.0 / 12.0, eps = 1e-6;
+    const double c13 = 1.0 / 3.0, c16 = 1.0 / 6.0, c56 = 5.0 / 6.0, c76 = 7.0 / 6.0, c116 = 11.0 / 6.0;
     double t, w;
-    t = (a - 2.0 * b) + c;
-    w = (a - 4.0 * b) + 3.0 * c;
-    const double b0 = k13 * (t * t) + 0.25 * (w * w);
-    t = (b - 2.0 * c) + d;
+    t = fma(-2.0, b, a) + c;
+    w = fma(3.0, c, fma(-4.0, b, a));
+    const double b0 = fma(k13 * t, t, 0.25 * (w * w));
+    t = fma(-2.0, c, b) + d;
     w = b - d;
-    const double b1 = k13 * (t * t) + 0.25 * (w * w);
-    t = (c - 2.0 * d) + e;
-    w = (3.0 * c - 4.0 * d) + e;
-    const double b2 = k13 * (t * t) + 0.25 * (w * w);
-    // alpha_k = d_k / s_k, s_k = (eps + beta_k)^2, scaled by s_0 s_1 s_2 (the
-    // normalised weights are unchanged): no division for the weights.
+    const double b1 = fma(k13 * t, t, 0.25 * (w * w));
+    t = fma(-2.0, d, c) + e;
+    w = fma(3.0, c, fma(-4.0, d, e));
+    const double b2 = fma(k13 * t, t, 0.25 * (w * w));
     const double s0 = (eps + b0) * (eps + b0);
     const double s1 = (eps + b1) * (eps + b1);
     const double s2 = (eps + b2) * (eps + b2);
     const double o0 = s1 * s2, o1 = s0 * s2, o2 = s0 * s1;
     {
-        const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * k6;
-        const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;
-        const double p2 = ((2.0 * c + 5.0 * d) - e) * k6;
+        const double p0 = fma(c116, c, fma(-c76, b, c13 * a));
+        const double p1 = fma(c13, d, fma(c56, c, -c16 * b));
+        const double p2 = fma(c13, c, fma(c56, d, -c16 * e));
         const double a0 = 0.1 * o0, a1 = 0.6 * o1, a2 = 0.3 * o2;
-        qp = ((a0 * p0 + a1 * p1) + a2 * p2) / ((a0 + a1) + a2);
+        qp = fma(a2, p2, fma(a1, p1, a0 * p0)) / ((a0 + a1) + a2);
     }
     {
-        const double p0 = ((2.0 * e - 7.0 * d) + 11.0 * c) * k6;
-        const double p1 = ((-d + 5.0 * c) + 2.0 * b) * k6;
-        const double p2 = ((2.0 * c + 5.0 * b) - a) * k6;
+        const double p0 = fma(c116, c, fma(-c76, d, c13 * e));
+        const double p1 = fma(c13, b, fma(c56, c, -c16 * d));
+        const double p2 = fma(c13, c, fma(c56, b, -c16 * a));
         const double a0 = 0.1 * o2, a1 = 0.6 * o1, a2 = 0.3 * o0;
-        qm = ((a0 * p0 + a1 * p1) + a2 * p2) / ((a0 + a1) + a2);
+        qm = fma(a2, p2, fma(a1, p1, a0 * p0)) / ((a0 + a1) + a2);
     }
 }
 
