@@ -44,7 +44,7 @@ struct hydro_ctx {
     const double *g_U = nullptr;
     const double *g_dt = nullptr;
     int g_cdt = -1;
-    // adjoint: line work lists per direction, 8x8 cell tiles, inverse links, scratch
+    // adjoint: line work lists per direction, 16x4 cell tiles, inverse links, scratch
     WorkItem *d_lines = nullptr;  // lines of every direction (cost field = direction | segment << 4)
     int nlines = 0;
     int nseg = 1;                 // segments per line
@@ -416,19 +416,21 @@ int setup_vjp(hydro_ctx *c)
     HIP_TRY(c, hipMalloc(&c->d_lines, sizeof(WorkItem) * std::max<size_t>(1, v.size())));
     if (!v.empty())
         HIP_TRY(c, hipMemcpy(c->d_lines, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
-    // cell tiles 8x8 over whole z columns
+    // cell tiles of 16 x 4 (a 128-byte row segment per tile row) over runs of
+    // at most 4 z planes, so that every wave has independent rows to load
     std::vector<WorkItem> ci;
     for (int b = 0; b < c->nblocks; ++b) {
         const hydro_block_t &B = c->hb[b];
         const int nz = (nd == 3) ? B.nz : 1;
-        for (int y0 = 0; y0 < B.ny; y0 += 8)
-            for (int x0 = 0; x0 < B.nx; x0 += 8) {
-                WorkItem w{};
-                w.block = b;
-                w.xy = x0 | (y0 << 16);
-                w.z = 0 | (nz << 16);
-                ci.push_back(w);
-            }
+        for (int z0 = 0; z0 < nz; z0 += 4)
+            for (int y0 = 0; y0 < B.ny; y0 += 4)
+                for (int x0 = 0; x0 < B.nx; x0 += 16) {
+                    WorkItem w{};
+                    w.block = b;
+                    w.xy = x0 | (y0 << 16);
+                    w.z = z0 | (std::min(4, nz - z0) << 16);
+                    ci.push_back(w);
+                }
     }
     c->ncitems = (int)ci.size();
     HIP_TRY(c, hipMalloc(&c->d_citems, sizeof(WorkItem) * std::max<size_t>(1, ci.size())));

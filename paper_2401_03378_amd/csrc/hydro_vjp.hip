@@ -654,11 +654,11 @@ hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hip
 {
     if (grid <= 0) return hipSuccess;
     if (ndim == 3) {
-        if (recon == kWENO) k_vjp_cells<3, 3, 8, 8><<<grid, 64, 0, st>>>(a);
-        else k_vjp_cells<3, 2, 8, 8><<<grid, 64, 0, st>>>(a);
+        if (recon == kWENO) k_vjp_cells<3, 3, 16, 4><<<grid, 64, 0, st>>>(a);
+        else k_vjp_cells<3, 2, 16, 4><<<grid, 64, 0, st>>>(a);
     } else {
-        if (recon == kWENO) k_vjp_cells<2, 3, 8, 8><<<grid, 64, 0, st>>>(a);
-        else k_vjp_cells<2, 2, 8, 8><<<grid, 64, 0, st>>>(a);
+        if (recon == kWENO) k_vjp_cells<2, 3, 16, 4><<<grid, 64, 0, st>>>(a);
+        else k_vjp_cells<2, 2, 16, 4><<<grid, 64, 0, st>>>(a);
     }
     return hipGetLastError();
 }
@@ -666,8 +666,8 @@ hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hip
 hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st)
 {
     if (grid <= 0) return hipSuccess;
-    if (ndim == 3) k_vjp_add<3, 8, 8><<<grid, 64, 0, st>>>(a);
-    else k_vjp_add<2, 8, 8><<<grid, 64, 0, st>>>(a);
+    if (ndim == 3) k_vjp_add<3, 16, 4><<<grid, 64, 0, st>>>(a);
+    else k_vjp_add<2, 16, 4><<<grid, 64, 0, st>>>(a);
     return hipGetLastError();
 }
 
