@@ -50,9 +50,11 @@ struct hydro_ctx {
     int nseg = 1;                 // segments per line
     WorkItem *d_citems = nullptr;
     int ncitems = 0;
+    WorkItem *d_xitems = nullptr;  // tiles of the x-line transpose
+    int nxitems = 0;
     int *d_inc_start = nullptr;
     int4 *d_inc = nullptr;
-    double *d_vjp = nullptr;     // gW per direction and segment | gA | gB, each nvar x ncell
+    double *d_vjp = nullptr;     // gW per direction and segment | gA | gB | UsT | gOutT, each nvar x ncell
     // telescoping: thick block copies, per-stage virtual (extended) blocks and work lists
     int tele_ready = 0;
     int ngt = 0;
@@ -436,6 +438,28 @@ int setup_vjp(hydro_ctx *c)
     HIP_TRY(c, hipMalloc(&c->d_citems, sizeof(WorkItem) * std::max<size_t>(1, ci.size())));
     if (!ci.empty())
         HIP_TRY(c, hipMemcpy(c->d_citems, ci.data(), sizeof(WorkItem) * ci.size(), hipMemcpyHostToDevice));
+    // x-line transpose: 16 positions x 16 rows of one plane per tile, positions -H .. nx+H-1
+    {
+        const int Hs = (c->prm.recon == HYDRO_WENO5) ? 3 : 2;
+        std::vector<WorkItem> xi;
+        for (int b = 0; b < c->nblocks; ++b) {
+            const hydro_block_t &B = c->hb[b];
+            const int nz = (nd == 3) ? B.nz : 1;
+            for (int k = 0; k < nz; ++k)
+                for (int j0 = 0; j0 < B.ny; j0 += 16)
+                    for (int p0 = 0; p0 < B.nx + 2 * Hs; p0 += 16) {
+                        WorkItem w{};
+                        w.block = b;
+                        w.xy = p0 | (j0 << 16);
+                        w.z = k;
+                        xi.push_back(w);
+                    }
+        }
+        c->nxitems = (int)xi.size();
+        HIP_TRY(c, hipMalloc(&c->d_xitems, sizeof(WorkItem) * std::max<size_t>(1, xi.size())));
+        if (!xi.empty())
+            HIP_TRY(c, hipMemcpy(c->d_xitems, xi.data(), sizeof(WorkItem) * xi.size(), hipMemcpyHostToDevice));
+    }
     // inverse links: for block b, every (block X, dir, side, kind) whose guards copy cells of b
     std::vector<std::vector<int4>> inc(c->nblocks);
     for (int x = 0; x < c->nblocks; ++x)
@@ -459,7 +483,7 @@ int setup_vjp(hydro_ctx *c)
     if (!flat.empty())
         HIP_TRY(c, hipMemcpy(c->d_inc, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice));
     const size_t per = (size_t)c->nv * (size_t)std::max<int64_t>(1, c->ncell);
-    if (hipMalloc(&c->d_vjp, sizeof(double) * per * (size_t)(nd * c->nseg + 2)) != hipSuccess) {
+    if (hipMalloc(&c->d_vjp, sizeof(double) * per * (size_t)(nd * c->nseg + 4)) != hipSuccess) {
         c->d_vjp = nullptr;
         return fail(c, HYDRO_ENOMEM, "adjoint scratch");
     }
@@ -815,6 +839,7 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
     HIP_TRY(c, hipMemsetAsync(gUn, 0, sizeof(double) * per, st));
     const size_t narr = (size_t)nd * c->nseg;
     double *gW = c->d_vjp, *gbuf[2] = {c->d_vjp + narr * per, c->d_vjp + (narr + 1) * per};
+    double *UsT = c->d_vjp + (narr + 2) * per, *gOutT = c->d_vjp + (narr + 3) * per;
     const double *g = gUnext;
     for (int s = S, q = 0; s >= 1; --s, q ^= 1) {
         VjpArgs v{};
@@ -841,6 +866,12 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         v.nseg = c->nseg;
         v.items = c->d_lines;
         v.nitems = c->nlines;
+        v.xitems = c->d_xitems;
+        v.nxitems = c->nxitems;
+        v.UsT = UsT;
+        v.gOutT = gOutT;
+        hipError_t ex = launch_vjp_xpose(v, nd, c->prm.recon, st);
+        if (ex != hipSuccess) return hip_fail(c, ex, "adjoint transpose launch");
         hipError_t el = launch_vjp_lines(v, nd, c->prm.recon, 0, c->nlines, st);
         if (el != hipSuccess) return hip_fail(c, el, "adjoint line launch");
         hipError_t e = launch_vjp_cells(v, nd, c->prm.recon, c->ncitems, st);
@@ -894,6 +925,7 @@ void hydro_destroy(hydro_ctx_t *c)
     (void)hipFree(c->d_vjp);
     (void)hipFree(c->d_lines);
     (void)hipFree(c->d_citems);
+    (void)hipFree(c->d_xitems);
     (void)hipFree(c->d_inc_start);
     (void)hipFree(c->d_inc);
     free_tele(c);

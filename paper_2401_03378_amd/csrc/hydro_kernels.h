@@ -56,7 +56,7 @@ struct VjpArgs {
     const FaceSrc *faces;
     const WorkItem *items;      // line work items: block, first line (xy), line count (z)
     int32_t nitems;
-    const WorkItem *citems;     // cell work items (8x8 tiles over z)
+    const WorkItem *citems;     // cell work items (16x4 tiles over runs of z planes)
     int32_t ncitems;
     int64_t nc;
     double gamma, g1, ig1;
@@ -71,6 +71,10 @@ struct VjpArgs {
     const int *inc_start;       // per block: range in inc
     const int4 *inc;            // guard positions copying this block: (block, dir, side, kind)
     int32_t nseg;               // requested segments per line (arrays per direction)
+    const WorkItem *xitems;     // transpose tiles: block, p tile | j tile << 16, k
+    int32_t nxitems;
+    double *UsT;                // Us along x lines, j fastest (positions -H .. nx+H-1)
+    double *gOutT;              // gOut along x lines, j fastest (interior positions)
 };
 
 hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, int variant, bool gather, int grid,
@@ -79,6 +83,7 @@ hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl
 hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_fill(const TeleArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick, hipStream_t st);
+hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t st);
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st);
 hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st);
 hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st);

@@ -347,6 +347,17 @@ __device__ __forceinline__ void seg_range(int n, int k, int s, int &f0, int &f1)
     f1 = min((s + 1) * L, n);
 }
 
+// Lines along x are read and written in a transposed order: element
+// (p, j, k) of block B, p in [-H, nx+H), sits at
+// off + (k (nx + 2H) + p + H) ny + j, so the lines of one wave (consecutive
+// j) touch consecutive addresses.  The block's padded footprint holds this
+// (H <= ng), so the transposed arrays share the state's block offsets.
+template <int H>
+__device__ __forceinline__ int64_t xt_at(const DevBlock &B, int p, int j, int k)
+{
+    return B.off + ((int64_t)k * (B.nx + 2 * H) + (p + H)) * B.ny + j;
+}
+
 // ------------------------------------------------------------ line kernel
 
 template <int D>
@@ -401,10 +412,11 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
     if (f0 >= 1) {        // flux difference of the cell left of the first face
         int i, j, k;
         line_coords<D>(f0 - 1, e1, e2, i, j, k);
-        const int64_t ci = cell_at(B, i, j, k);
+        const int64_t ci = (D == 0) ? xt_at<H>(B, i, j, k) : cell_at(B, i, j, k);
+        const double *gO = (D == 0) ? A.gOutT : A.gOut;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double gT = A.b * A.gOut[v * nc + ci];
+            const double gT = A.b * gO[v * nc + ci];
             gD_prev[v] = -(dt * gT) * id;
         }
     }
@@ -413,7 +425,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
     auto emit = [&](int p, const double (&gw)[5]) {
         int i, j, k;
         line_coords<D>(p, e1, e2, i, j, k);
-        const int64_t ci = cell_at(B, i, j, k);
+        const int64_t ci = (D == 0) ? xt_at<H>(B, i, j, k) : cell_at(B, i, j, k);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             if (NDIM == 2 && v == 3) continue;
@@ -431,7 +443,10 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
             int i, j, k;
             line_coords<D>(t, e1, e2, i, j, k);
             double u[5];
-            load_cons<NDIM>(A.Us, nc, src_cell<D, true>(B, F6, i, j, k), u);
+            if constexpr (D == 0)
+                load_cons<NDIM>(A.UsT, nc, xt_at<H>(B, i, j, k), u);
+            else
+                load_cons<NDIM>(A.Us, nc, src_cell<D, true>(B, F6, i, j, k), u);
             eos<NDIM>(u, Wwin[NWIN - 1], K.g1);
         }
         const int c = t - R;          // reconstruction cell completed by this position
@@ -449,10 +464,11 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
                 if (c < n) {
                     int i, j, k;
                     line_coords<D>(c, e1, e2, i, j, k);
-                    const int64_t ci = cell_at(B, i, j, k);
+                    const int64_t ci = (D == 0) ? xt_at<H>(B, i, j, k) : cell_at(B, i, j, k);
+                    const double *gO = (D == 0) ? A.gOutT : A.gOut;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        const double gT = A.b * A.gOut[v * nc + ci];
+                        const double gT = A.b * gO[v * nc + ci];
                         gD[v] = -(dt * gT) * id;
                     }
                 }
@@ -574,7 +590,7 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
             double gw[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) gw[v] = 0.0;
-            seg_sum(B, 0, i, ci, gw);
+            seg_sum(B, 0, i, xt_at<H>(B, i, j, k), gw);
             seg_sum(B, 1, j, ci, gw);
             if constexpr (NDIM == 3) seg_sum(B, 2, k, ci, gw);
             // guard positions (of this or other blocks) that copy this cell
@@ -596,7 +612,7 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
                 for (int l = lo; l <= hi; ++l) {
                     const int gpos = gp0 + step * l;
                     const int gi = (d == 0) ? gpos : i, gj = (d == 1) ? gpos : j, gk = (d == 2) ? gpos : k;
-                    seg_sum(X, d, gpos, cell_at(X, gi, gj, gk), gw);
+                    seg_sum(X, d, gpos, (d == 0) ? xt_at<H>(X, gi, gj, gk) : cell_at(X, gi, gj, gk), gw);
                 }
             }
             double u[5], gu[5];
@@ -634,7 +650,70 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_add(VjpArgs A)
     }
 }
 
+// Stage input and output cotangent of every block in the transposed x-line
+// order (see xt_at): Us at positions -H .. nx+H-1, guard positions gathered
+// from their sources, and gOut at the interior positions.  A workgroup takes
+// a 16-position x 16-row tile of one plane through LDS, reading along x and
+// writing along y.
+template <int NDIM, int H>
+__global__ void __launch_bounds__(256) k_vjp_xpose(VjpArgs A)
+{
+    constexpr int NV = NDIM + 2;
+    __shared__ double sU[NV][16][17];
+    __shared__ double sG[NV][16][17];
+    const int tid = threadIdx.x;
+    const int64_t nc = A.nc;
+    for (int w = blockIdx.x; w < A.nxitems; w += gridDim.x) {
+        const WorkItem it = A.xitems[w];
+        const DevBlock B = A.blocks[it.block];
+        const FaceSrc *F6 = A.faces + 6 * (int64_t)it.block;
+        const int p0 = (it.xy & 0xffff) - H, j0 = it.xy >> 16, k = it.z;
+        {
+            const int tp = tid % 16, tj = tid / 16;
+            const int p = p0 + tp, j = j0 + tj;
+            if (p < B.nx + H && j < B.ny) {
+                const int64_t src = src_cell<0, true>(B, F6, p, j, k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sU[v][tj][tp] = A.Us[v * nc + src];
+                if (p >= 0 && p < B.nx) {
+                    const int64_t ci = cell_at(B, p, j, k);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sG[v][tj][tp] = A.gOut[v * nc + ci];
+                }
+            }
+        }
+        __syncthreads();
+        {
+            const int tj = tid % 16, tp = tid / 16;
+            const int p = p0 + tp, j = j0 + tj;
+            if (p < B.nx + H && j < B.ny) {
+                const int64_t ti = xt_at<H>(B, p, j, k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) A.UsT[v * nc + ti] = sU[v][tj][tp];
+                if (p >= 0 && p < B.nx) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) A.gOutT[v * nc + ti] = sG[v][tj][tp];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------- launchers
+
+hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t st)
+{
+    if (a.nxitems <= 0) return hipSuccess;
+    if (ndim == 3) {
+        if (recon == kWENO) k_vjp_xpose<3, 3><<<a.nxitems, 256, 0, st>>>(a);
+        else k_vjp_xpose<3, 2><<<a.nxitems, 256, 0, st>>>(a);
+    } else {
+        if (recon == kWENO) k_vjp_xpose<2, 3><<<a.nxitems, 256, 0, st>>>(a);
+        else k_vjp_xpose<2, 2><<<a.nxitems, 256, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st)
 {
