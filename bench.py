@@ -71,8 +71,8 @@ def extras(S, prob, U0, ms_per_step):
     from paper_2401_03378_amd.adjoint import rollout, rollout_vjp, TorchStepper
     st = TorchStepper(S)
     n, k = prob.nsteps, 5
-    UN, tape = rollout(st, U0, 2, 1)                 # warm-up: graph, adjoint scratch
-    rollout_vjp(st, tape, torch.nan_to_num(UN))
+    UN, tape = rollout(st, U0, n, k)                 # warm-up of the same shape: graph,
+    rollout_vjp(st, tape, torch.nan_to_num(UN))      # adjoint scratch, allocator blocks
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     UN, tape = rollout(st, U0, n, n + 1)

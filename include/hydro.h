@@ -143,7 +143,11 @@ int hydro_rk_stage(hydro_ctx_t *ctx, int32_t stage, const double *dt_dev,
                    const double *Un, const double *Us, double *Uout);
 
 /* One full step in place on U.  If compute_dt != 0 the CFL dt of U is first
- * written to dt_dev; otherwise the value already in dt_dev is used. */
+ * written to dt_dev; otherwise the value already in dt_dev is used.  With
+ * use_graph, the step is captured into a hipGraph bound to (U, dt_dev,
+ * compute_dt) once the same arguments arrive in two consecutive calls, and
+ * replayed while they stay the same; other calls launch the kernels
+ * directly.  Either way the result is the same bit for bit. */
 int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
 
 /* Vector-Jacobian product of one step with dt held fixed (the branch

@@ -44,6 +44,9 @@ struct hydro_ctx {
     const double *g_U = nullptr;
     const double *g_dt = nullptr;
     int g_cdt = -1;
+    const double *l_U = nullptr;    // arguments of the previous hydro_step call
+    const double *l_dt = nullptr;
+    int l_cdt = -1;
     // adjoint: line work lists per direction, 16x4 cell tiles, inverse links, scratch
     WorkItem *d_lines = nullptr;  // lines of every direction (cost field = direction | segment << 4)
     int nlines = 0;
@@ -792,7 +795,17 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
     if (!c->tune.use_graph || c->tune.mode == HYDRO_MODE_PERBLOCK)
         return enqueue_step(c, U, dt_dev, compute_dt, c->stream);
     const int cdt = compute_dt ? 1 : 0;
-    if (!c->gexec || c->g_U != U || c->g_dt != dt_dev || c->g_cdt != cdt) {
+    // The graph is bound to (U, dt, compute_dt).  A call with other arguments
+    // is launched directly; it is captured only when the same arguments come
+    // twice in a row, so callers that step ever-new buffers (a recomputation
+    // from checkpoints) pay no capture per step.
+    const bool repeat = (c->l_U == U && c->l_dt == dt_dev && c->l_cdt == cdt);
+    c->l_U = U;
+    c->l_dt = dt_dev;
+    c->l_cdt = cdt;
+    const bool bound = c->gexec && c->g_U == U && c->g_dt == dt_dev && c->g_cdt == cdt;
+    if (!bound && !repeat) return enqueue_step(c, U, dt_dev, cdt, c->stream);
+    if (!bound) {
         drop_graph(c);
         HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
         int rc = enqueue_step(c, U, dt_dev, cdt, c->cap);
