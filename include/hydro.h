@@ -108,7 +108,10 @@ int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks,
 /* Create a context on the current HIP device for the given problem; work is
  * enqueued on `stream` (a hipStream_t; NULL = default stream).  Validates as
  * hydro_validate, uploads the tables, allocates stage buffers and picks a
- * default tuning.  *out receives the context (NULL on error). */
+ * default tuning.  *out receives the context (NULL on error).  A problem with
+ * no blocks is valid: hydro_step, hydro_rk_stage, hydro_fill_guards and
+ * hydro_step_vjp then enqueue nothing and leave their arrays untouched, and
+ * hydro_cfl_dt returns HYDRO_EINVAL (no cell bounds the step). */
 int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks,
                  const hydro_link_t *links, int32_t nblocks, int64_t ncell_total,
                  void *stream, hydro_ctx_t **out);

@@ -119,6 +119,27 @@ def test_turbulence_step_vjp_full_size():
     S.close()
 
 
+def test_sedov_step_vjp_full_size_and_rollout():
+    """The bench workload: the step VJP at full size (outflow faces, the
+    strong shock, positivity fallbacks) and a 4-step checkpointed rollout."""
+    p = W.config(1)
+    dt = O.cfl_dt(p, p.U0)
+    g = _rand_cot(p, 8)
+    ref = O.step_vjp(p, p.U0, dt, g)
+    S = _solver(p)
+    got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
+    assert_parity(p, got, ref, "sedov vjp 128^3")
+    ost = OracleStepper(p)
+    _, tape_o = rollout(ost, p.U0, 4, 2)
+    g_o = rollout_vjp(ost, tape_o, g)
+    st = TorchStepper(S)
+    _, tape_g = rollout(st, S.to_device(p.U0), 4, 2)
+    assert tape_g.dts == tape_o.dts
+    g_g = rollout_vjp(st, tape_g, S.to_device(g)).cpu().numpy()
+    assert_parity(p, g_g, g_o, "sedov 4-step rollout gradient")
+    S.close()
+
+
 def test_turbulence_rollout_small():
     p = W.turb3d(N=64, n=16, seed=3)
     rng = np.random.default_rng(6)

@@ -190,6 +190,59 @@ def test_graph_replays_are_identical():
     S.close()
 
 
+def test_fresh_buffers_and_graph_replay_agree():
+    """hydro_step captures a graph only for repeated arguments; steps on a
+    fresh buffer each time (direct launches), steps in place (graph replay)
+    and alternating fixed and CFL dt all give the same bits."""
+    p = W.random_blocks(3, 12, 3, seed=9, recon=1, rk=3, bc="outflow", NB=(2, 2, 1))
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    S = _solver(p)
+    U1 = S.to_device(p.U0)
+    for _ in range(4):
+        S.step(U1)
+    U2 = S.to_device(p.U0)
+    for _ in range(4):
+        V = U2.clone()
+        S.step(V)
+        U2 = V
+    assert np.array_equal(U1.cpu().numpy()[:, m], U2.cpu().numpy()[:, m])
+    U3 = S.to_device(p.U0)
+    U4 = S.to_device(p.U0)
+    for n in range(4):
+        dt = S.cfl_dt(U3).clone()
+        S.step(U3, dt)
+        S.step(U4)
+    assert np.array_equal(U3.cpu().numpy()[:, m], U1.cpu().numpy()[:, m])
+    assert np.array_equal(U4.cpu().numpy()[:, m], U1.cpu().numpy()[:, m])
+    S.status()
+    S.close()
+
+
+def test_problem_without_blocks():
+    """No blocks: the step, stage and adjoint calls are no-ops that leave
+    their arrays untouched; the CFL dt has no cells to bound it (EINVAL)."""
+    from paper_2401_03378_amd._hip import HydroError, HYDRO_EINVAL
+    p = W.random_blocks(2, 8, 2, seed=1, NB=(1, 1, 1))
+    p.blocks = p.blocks[:0]
+    p.links = p.links[:0]
+    S = _solver(p)
+    U = S.to_device(p.U0)
+    before = U.clone()
+    S.step(U, 1e-3)
+    S.rk_stage(1, U, U.clone(), U)
+    g = torch.zeros_like(U)
+    out = torch.full_like(U, 7.0)
+    S.step_vjp(U, g, 1e-3, out)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(U), torch.nan_to_num(before))
+    assert torch.all(out == 7.0)
+    with pytest.raises(HydroError) as e:
+        S.cfl_dt(U)
+    assert e.value.code == HYDRO_EINVAL
+    S.status()
+    S.close()
+
+
 def test_free_stream_gpu():
     p = W.random_blocks(3, 8, 3, seed=0, recon=1, rk=2)
     m = W.interior_mask(p.blocks, p.ncell, 3)
