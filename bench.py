@@ -31,6 +31,7 @@ FLOPS_PER_ZONE_STAGE = {("3", "WENO5"): 1781, ("3", "PLM"): 476, ("2", "PLM"): 2
 # write U_{s+1}; interior cells only.
 PEAK_FP64 = 78.6e12          # 256 CU x 64 lanes x 2.4 GHz x 2 (fma)
 PEAK_HBM = 8.0e12
+PEAK_VALU_LANES = 256 * 64 * 2.4e9   # FP64 lane-instructions per second (16-lane SIMDs, 4 per CU)
 
 
 def log(*a):
@@ -180,11 +181,25 @@ def main():
             "frac": round(achieved * 1e12 / PEAK_FP64, 4), "traffic": None,
             "kernel": "k_stage (fused guard-gather+EOS+WENO5+HLLC+update)",
             "avg_launch_s": t_stage, "flops_per_launch": flops}
-    tr_path = os.path.join(ROOT, "profiles", "traffic_stage_sedov128.json")
-    if os.path.exists(tr_path):
-        tr = json.load(open(tr_path))
-        if tr.get("source_sha") == source_hash():
-            roof["traffic"] = tr["bytes_per_launch"]
+    # counter-derived figures, valid while the kernel source and the launch
+    # configuration are those they were measured with
+    def measured(name):
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            return None
+        rec = json.load(open(path))
+        if rec.get("source_sha") != source_hash() or rec.get("tuning") != S.tuning():
+            return None
+        return rec
+    tr = measured("traffic_stage_sedov128.json")
+    if tr:
+        roof["traffic"] = tr["bytes_per_launch"]
+    ct = measured("counters_stage_sedov128.json")
+    if ct:
+        # issued VALU lane-instructions (rocprofv3 SQ_INSTS_VALU x 64) over the
+        # chip's FP64 instruction rate: how busy the vector units are
+        roof["valu_issue_frac"] = round(ct["valu_lane_instr_per_launch"] / t_stage / PEAK_VALU_LANES, 4)
+        roof["valu_lane_instr_per_zone_stage"] = round(ct["valu_lane_instr_per_launch"] / zones)
     # bytes the method must move per stage (RK3 average: read U_s, U^n for
     # s >= 2, write U_{s+1}) relative to HBM peak at the whole-step rate
     balg = (3 * 40 + 2 * 40 + 3 * 40) / 3.0
