@@ -117,7 +117,7 @@ def main():
                     help="skip the adjoint/forward and per-block-launch comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the step runs on one GPU (blocks are not sharded across GPUs); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -885,7 +885,7 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         v.gOutT = gOutT;
         hipError_t ex = launch_vjp_xpose(v, nd, c->prm.recon, st);
         if (ex != hipSuccess) return hip_fail(c, ex, "adjoint transpose launch");
-        hipError_t el = launch_vjp_lines(v, nd, c->prm.recon, 0, c->nlines, st);
+        hipError_t el = launch_vjp_lines(v, nd, c->prm.recon, c->nlines, st);
         if (el != hipSuccess) return hip_fail(c, el, "adjoint line launch");
         hipError_t e = launch_vjp_cells(v, nd, c->prm.recon, c->ncitems, st);
         if (e != hipSuccess) return hip_fail(c, e, "adjoint cell launch");

@@ -84,7 +84,7 @@ hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_
 hipError_t launch_tele_fill(const TeleArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick, hipStream_t st);
 hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t st);
-hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st);
+hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int nitems, hipStream_t st);
 hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st);
 hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st);
 

@@ -715,9 +715,8 @@ hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int d, int nitems, hipStream_t st)
+hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int nitems, hipStream_t st)
 {
-    (void)d;
     if (nitems <= 0) return hipSuccess;
     if (ndim == 3) {
         if (recon == kWENO) k_vjp_lines<3, kWENO><<<nitems, 64, 0, st>>>(a);
