@@ -156,7 +156,11 @@ int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
 /* Vector-Jacobian product of one step with dt held fixed (the branch
  * decisions of limiters, fallback and Riemann solver are those of the forward
  * step at Un): gUn = (dU^{n+1}/dU^n)^T gUnext over interior cells; the
- * padding of gUn is set to 0.  gUn must not alias gUnext. */
+ * padding of gUn is set to 0.  gUn must not alias gUnext.  It recomputes the
+ * stage inputs from Un (no tape), is asynchronous, and is deterministic (no
+ * atomics; linear in gUnext bit for bit).  The first call allocates the
+ * ctx's adjoint scratch, (ndim x line segments + 4) x nvar x ncell_total
+ * doubles, kept until hydro_destroy (HYDRO_ENOMEM if it cannot). */
 int hydro_step_vjp(hydro_ctx_t *ctx, const double *Un, const double *dt_dev,
                    const double *gUnext, double *gUn);
 
@@ -168,6 +172,8 @@ int hydro_status(hydro_ctx_t *ctx, int64_t *n_nonphys);
 /* Text of the last error on this ctx (valid until the next call on it). */
 const char *hydro_last_error(hydro_ctx_t *ctx);
 
+/* Wait for the ctx's stream, then release the ctx and all device memory it
+ * owns.  NULL is ignored. */
 void hydro_destroy(hydro_ctx_t *ctx);
 
 #ifdef __cplusplus
