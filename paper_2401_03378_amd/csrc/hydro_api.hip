@@ -873,7 +873,8 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         v.gOut = g;
         v.gW = gW;
         v.gUs = gbuf[q];
-        v.gUn = (s >= 2) ? gUn : nullptr;
+        v.gUn = gUn;                 // s >= 2: += a gOut; s = 1: += gU_1
+        v.last = (s == 1) ? 1 : 0;
         v.inc_start = c->d_inc_start;
         v.inc = c->d_inc;
         v.nseg = c->nseg;
@@ -891,15 +892,6 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         if (e != hipSuccess) return hip_fail(c, e, "adjoint cell launch");
         g = gbuf[q];
     }
-    VjpArgs v{};
-    v.blocks = c->d_blocks;
-    v.citems = c->d_citems;
-    v.ncitems = c->ncitems;
-    v.nc = c->ncell;
-    v.gUs = const_cast<double *>(g);
-    v.gUn = gUn;
-    hipError_t e = launch_vjp_add(v, nd, c->ncitems, st);
-    if (e != hipSuccess) return hip_fail(c, e, "adjoint add launch");
     return HYDRO_OK;
 }
 

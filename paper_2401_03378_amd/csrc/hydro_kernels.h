@@ -68,6 +68,7 @@ struct VjpArgs {
     double *gW;                 // padded primitive cotangents, nvar x nc
     double *gUs;                // cotangent of the stage input (interior)
     double *gUn;                // += a gOut (null: skip)
+    int32_t last;               // first stage: gU_s goes straight into gUn (gUn += gU_s), gUs unused
     const int *inc_start;       // per block: range in inc
     const int4 *inc;            // guard positions copying this block: (block, dir, side, kind)
     int32_t nseg;               // requested segments per line (arrays per direction)
@@ -86,6 +87,5 @@ hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick
 hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t st);
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int nitems, hipStream_t st);
 hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st);
-hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st);
 
 }  // namespace hydro

@@ -13,14 +13,17 @@
 //                  primitives, and writes the primitive cotangent of every
 //                  position the line's stencils read (interior and guard
 //                  positions) into a padded array of its own direction, so no
-//                  two threads write one element.
+//                  two threads write one element.  Lines along x work on a
+//                  transposed copy of their inputs (k_vjp_xpose), so that the
+//                  lines of a wave read and write consecutive addresses.
 //  k_vjp_cells     one thread per interior cell: sums the arrays of the
 //                  directions and line segments that cover it in a fixed
 //                  order (x, y, z; segments in order), adds the cotangents of the
 //                  guard positions that are copies of the cell (through the
 //                  inverse link table; neighbour, periodic and outflow
 //                  copies), applies the EOS transpose and forms
-//                  gU_s = b gOut + (dW/dU)^T gW, gU^n += a gOut.
+//                  gU_s = b gOut + (dW/dU)^T gW, gU^n += a gOut (for the
+//                  first stage, whose input is U^n: gU^n += gU_s).
 // The guard-fill transpose is thus a deterministic gather, not an atomic
 // scatter.
 #include "hydro_kernels.h"
@@ -621,31 +624,14 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const double go = A.gOut[v * nc + ci];
-                A.gUs[v * nc + ci] = A.b * go + gu[v];
-                if (A.gUn) A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + A.a * go;
+                const double gs = A.b * go + gu[v];
+                if (A.last) {
+                    A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + gs;
+                } else {
+                    A.gUs[v * nc + ci] = gs;
+                    if (A.gUn) A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + A.a * go;
+                }
             }
-        }
-    }
-}
-
-// Final accumulation gUn += g (cotangent of the first stage's input U^n).
-template <int NDIM, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY) k_vjp_add(VjpArgs A)
-{
-    constexpr int NV = NDIM + 2;
-    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
-    const int64_t nc = A.nc;
-    for (int w = blockIdx.x; w < A.ncitems; w += gridDim.x) {
-        const WorkItem it = A.citems[w];
-        const DevBlock B = A.blocks[it.block];
-        const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
-        const int z0 = it.z & 0xffff, nzc = it.z >> 16;
-        const int i = x0 + tx, j = y0 + ty;
-        if (i >= B.nx || j >= B.ny) continue;
-        for (int k = z0; k < z0 + nzc; ++k) {
-            const int64_t ci = cell_at(B, i, j, k);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + A.gUs[v * nc + ci];
         }
     }
 }
@@ -738,14 +724,6 @@ hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hip
         if (recon == kWENO) k_vjp_cells<2, 3, 16, 4><<<grid, 64, 0, st>>>(a);
         else k_vjp_cells<2, 2, 16, 4><<<grid, 64, 0, st>>>(a);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_vjp_add(const VjpArgs &a, int ndim, int grid, hipStream_t st)
-{
-    if (grid <= 0) return hipSuccess;
-    if (ndim == 3) k_vjp_add<3, 16, 4><<<grid, 64, 0, st>>>(a);
-    else k_vjp_add<2, 16, 4><<<grid, 64, 0, st>>>(a);
     return hipGetLastError();
 }
 
