@@ -91,7 +91,9 @@ typedef struct {
     int32_t grid;       /* workgroups of a persistent launch; 0 = one per work item */
     int32_t zchunk;     /* z planes per work item; 0 = the whole block */
     int32_t use_graph;  /* replay hydro_step from a captured hipGraph */
-    int32_t xcd;        /* place a block's work items on one XCD (L2) */
+    int32_t xcd;        /* 0: list order; 1: a block's work items on one XCD (L2), blocks
+                           dealt round-robin; 2: the same with contiguous ranges of
+                           block indices per XCD (neighbours share an L2) */
     int32_t variant;    /* stage schedule: 0 plain, 1 loads of the next plane issued a plane ahead */
 } hydro_tuning_t;
 

@@ -5,8 +5,11 @@ tile shape (8x8, 16x8, 16x16 columns per work item), z-chunking of work
 items, the persistent grid size and the XCD placement of a block's work
 items.  Every candidate must reproduce the reference candidate's state bit
 for bit after two steps (the kernels are deterministic and the launch shape
-must not change a single rounding), then the fastest by timed steps wins.
-Results are cached in a JSON file keyed by device and problem signature.
+must not change a single rounding), then the candidates within 3% of the
+fastest are timed twice more; among those within 1% of the best time the
+first in preference order wins (the block-range XCD placement, which re-reads
+the fewest halo bytes from HBM, and whole blocks come first).  Results are
+cached in a JSON file keyed by device and problem signature.
 """
 from __future__ import annotations
 
@@ -34,18 +37,24 @@ def signature(prob, arch=None) -> str:
 
 
 def candidates(prob, ncu):
+    """Launch configurations to time, in order of preference when times tie:
+    the block-range XCD placement (fewest HBM re-reads of halos) and whole
+    blocks first."""
     out = []
     zch = [0] if prob.ndim == 2 else [0, 8]
     for variant in (0, 1):
-        for tile in (0, 1, 2):
-            for zc in zch:
-                for grid in (0, 2 * ncu, 4 * ncu):
-                    for xcd in (0, 1):
-                        if xcd and grid == 0:
+        for tile in (2, 1, 0):
+            for xcd in (2, 1, 0):
+                for zc in zch:
+                    for grid in (0, 2 * ncu, 4 * ncu):
+                        if xcd == 1 and grid == 0:
                             continue
                         out.append(dict(mode=0, tile=tile, zchunk=zc, grid=grid, xcd=xcd, use_graph=1,
                                         variant=variant))
     return out
+
+
+TIE = 0.01   # candidates within 1% of the fastest count as equally fast
 
 
 def _time_steps(S, U, nsteps):
@@ -76,10 +85,23 @@ def search(S, prob, nsteps=5, log=print):
         t = _time_steps(S, U, nsteps)
         results.append((t, cand))
         log(f"autotune {cand}: {t * 1e3:.3f} ms/step")
-        if best is None or t < best[0]:
-            best = (t, cand)
-    S.set_tuning(**best[1])
-    return best[1], results
+    # re-time the candidates close to the fastest (keeping each one's best
+    # time) so that timing noise does not decide between them
+    tmin = min(t for t, _ in results)
+    close = [[t, c] for t, c in results if t <= tmin * (1.0 + 3 * TIE)]
+    for _ in range(2):
+        for entry in close:
+            S.set_tuning(**entry[1])
+            U = U0.clone()
+            S.step(U)
+            S.step(U)
+            entry[0] = min(entry[0], _time_steps(S, U, nsteps))
+    S.status()
+    tmin = min(t for t, _ in close)
+    best = next(c for t, c in close if t <= tmin * (1.0 + TIE))
+    log(f"autotune choice {best}: {tmin * 1e3:.3f} ms/step (fastest of {len(close)} close candidates)")
+    S.set_tuning(**best)
+    return best, results
 
 
 def tuned_or_search(S, prob, log=print, cache=None):

@@ -185,9 +185,14 @@ int tile_x(int t) { return t == 0 ? 8 : 16; }
 int tile_y(int t) { return t == 2 ? 16 : 8; }
 
 // Work items: xy tiles of every block over z chunks.  The persistent list is
-// sorted by decreasing size (largest first); with xcd != 0 the items of one
-// block are placed at list positions congruent modulo 8, so a fixed-stride
-// persistent grid (a multiple of 8 workgroups) keeps them on one XCD.
+// sorted by decreasing size (largest first).  With xcd != 0 the items of one
+// block are placed at list positions congruent modulo 8, so that workgroups
+// dealt round-robin onto the 8 XCDs (one per item, or a persistent grid of a
+// multiple of 8) keep them on one XCD: xcd = 1 deals the blocks round-robin
+// onto the 8 positions; xcd = 2 gives each position a contiguous range of
+// block indices of about equal work, so blocks that are neighbours in the
+// block order also share an L2 and one's halo reads can hit the lines the
+// other brought in.
 void build_items(hydro_ctx *c, std::vector<WorkItem> &list, std::vector<WorkItem> &perblock, std::vector<int> &start)
 {
     const int TX = tile_x(c->tune.tile), TY = tile_y(c->tune.tile);
@@ -219,11 +224,22 @@ void build_items(hydro_ctx *c, std::vector<WorkItem> &list, std::vector<WorkItem
         // order, then interleave the lanes position by position
         std::vector<std::vector<WorkItem>> lane(8);
         std::vector<int> lane_of(c->nblocks, -1);
-        int next = 0;
-        for (const WorkItem &w : list) {
-            if (lane_of[w.block] < 0) lane_of[w.block] = (next++) % 8;
-            lane[lane_of[w.block]].push_back(w);
+        if (c->tune.xcd == 2) {
+            std::vector<double> cost(c->nblocks, 0.0);
+            double total = 0.0;
+            for (const WorkItem &w : perblock) { cost[w.block] += w.cost; total += w.cost; }
+            double before = 0.0;
+            for (int b = 0; b < c->nblocks; ++b) {
+                const double mid = before + 0.5 * cost[b];
+                lane_of[b] = std::min(7, (int)(8.0 * mid / std::max(total, 1.0)));
+                before += cost[b];
+            }
+        } else {
+            int next = 0;
+            for (const WorkItem &w : list)
+                if (lane_of[w.block] < 0) lane_of[w.block] = (next++) % 8;
         }
+        for (const WorkItem &w : list) lane[lane_of[w.block]].push_back(w);
         std::vector<WorkItem> out;
         out.reserve(list.size());
         size_t maxl = 0;
@@ -738,7 +754,8 @@ int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
     if (!c || !t) return HYDRO_EINVAL;
     if (t->mode != HYDRO_MODE_PERSISTENT && t->mode != HYDRO_MODE_PERBLOCK && t->mode != HYDRO_MODE_TELESCOPING)
         return fail(c, HYDRO_EINVAL, "mode");
-    if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0 || t->variant < 0 || t->variant > 1)
+    if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0 || t->variant < 0 || t->variant > 1 ||
+        t->xcd < 0 || t->xcd > 2)
         return fail(c, HYDRO_EINVAL, "tuning range");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);

@@ -128,6 +128,7 @@ def test_turbulence_small_all_steps():
 
 
 @pytest.mark.parametrize("mode_kw", [dict(mode=1), dict(use_graph=0), dict(grid=37), dict(grid=256, xcd=1),
+                                     dict(xcd=2), dict(grid=512, xcd=2, zchunk=4),
                                      dict(variant=1), dict(mode=1, variant=1)])
 def test_launch_forms_bitwise_identical(mode_kw):
     """Per-block launches, no graph, odd persistent grids and the XCD
