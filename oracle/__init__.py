@@ -37,6 +37,10 @@ class _Link(C.Structure):
     _fields_ = [("nbr", C.c_int32 * 6)]
 
 
+class _Amr(C.Structure):
+    _fields_ = [("level", C.c_int32), ("kind", C.c_int32 * 6), ("nbr", (C.c_int32 * 4) * 6)]
+
+
 class _Problem(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("recon", C.c_int32), ("rk", C.c_int32),
                 ("nblocks", C.c_int32), ("ncell", C.c_int64),
@@ -80,6 +84,10 @@ def lib():
             "ora_cs_plm_n": (None, [i64, dp, dp, dp, dp, dp, dp]),
             "ora_cs_weno5_n": (None, [i64, dp, dp, dp, dp, dp, dp]),
             "ora_cs_hllc_n": (None, [P, i64, C.c_int, dp, dp, dp, dp, dp, dp]),
+            "ora_amr_validate": (C.c_int, [P, C.c_void_p]),
+            "ora_amr_fill_guards": (C.c_int, [P, C.c_void_p, dp]),
+            "ora_amr_cfl_dt": (C.c_int, [P, C.c_void_p, dp, dp]),
+            "ora_amr_step": (C.c_int, [P, C.c_void_p, dp, dp, C.c_int, C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -117,6 +125,17 @@ class Problem:
         for i, l in enumerate(links):
             for f in range(6):
                 self._links[i].nbr[f] = int(l["nbr"][f])
+        amr = override.get("amr", getattr(prob, "amr", None))
+        self._amr = None
+        if amr is not None:
+            amr = np.ascontiguousarray(amr)
+            self._amr = (_Amr * max(len(amr), 1))()
+            for i, a in enumerate(amr):
+                self._amr[i].level = int(a["level"])
+                for f in range(6):
+                    self._amr[i].kind[f] = int(a["kind"][f])
+                    for h in range(4):
+                        self._amr[i].nbr[f][h] = int(a["nbr"][f][h])
         self.c = _Problem(self.ndim, int(get("recon")), int(get("rk")), len(blocks),
                           self.ncell, float(get("gamma")), float(get("cfl")),
                           float(get("dx")), float(get("dy")), float(get("dz")),
@@ -172,6 +191,50 @@ def step_telescoping(prob, U, dt=None) -> float:
     d = np.array([0.0 if dt is None else float(dt)])
     _check(lib().ora_step_telescoping(P.ptr, _dp(U), _dp(d), 1 if dt is None else 0), "step_telescoping")
     return float(d[0])
+
+
+# ------------------------------------------------------------------- AMR
+
+AMR_ALL_LEVELS, AMR_LEVEL_BY_LEVEL, AMR_NO_CORRECTION = 0, 1, 2
+
+
+def _amr_args(prob):
+    P = _as_problem(prob)
+    if P._amr is None:
+        raise ValueError("problem has no AMR table")
+    return P, C.cast(P._amr, C.c_void_p)
+
+
+def amr_validate(prob) -> int:
+    P, A = _amr_args(prob)
+    return lib().ora_amr_validate(P.ptr, A)
+
+
+def amr_fill_guards(prob, U):
+    P, A = _amr_args(prob)
+    _check(lib().ora_amr_fill_guards(P.ptr, A, _dp(U)), "amr_fill_guards")
+
+
+def amr_cfl_dt(prob, U) -> float:
+    P, A = _amr_args(prob)
+    dt = np.zeros(1)
+    _check(lib().ora_amr_cfl_dt(P.ptr, A, _dp(U), _dp(dt)), "amr_cfl_dt")
+    return float(dt[0])
+
+
+def amr_step(prob, U, dt=None, order=AMR_ALL_LEVELS) -> float:
+    """One step on a mesh with refinement levels, in place; order: flux
+    correction for all levels at once, level by level, or (a check only)
+    none.  Returns the dt used."""
+    P, A = _amr_args(prob)
+    d = np.array([0.0 if dt is None else float(dt)])
+    _check(lib().ora_amr_step(P.ptr, A, _dp(U), _dp(d), 1 if dt is None else 0, int(order)), "amr_step")
+    return float(d[0])
+
+
+def amr_run(prob, U, nsteps, order=AMR_ALL_LEVELS, dts=None):
+    P = _as_problem(prob)
+    return [amr_step(P, U, None if dts is None else dts[n], order) for n in range(nsteps)]
 
 
 def run(prob, U, nsteps, dts=None):

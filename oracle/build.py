@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["oracle.c", "oracle_cs.c"]
+SOURCES = ["oracle.c", "oracle_cs.c", "oracle_amr.c"]
 
 
 def build(verbose=False):

@@ -38,6 +38,20 @@ typedef struct {
     const ora_link *links;
 } ora_problem;
 
+/* Two-level-ratio block AMR (refinement ratio 2, levels differ by at most
+ * one across a face).  A face whose link is ORA_LEVEL_FACE touches blocks of
+ * another level: kind 1, one coarser block, of whose face this block's face
+ * covers the part starting at coarse cells (o1, o2) along the face's two
+ * transverse axes (x, y, z order); kind 2, the 2^(ndim-1) finer blocks that
+ * cover the face, listed as nbr[face][h1 + 2 h2] by transverse half.  All
+ * blocks of an AMR problem share nx, ny, nz and ng. */
+#define ORA_LEVEL_FACE (-3)
+typedef struct {
+    int32_t level;          /* 0 = coarsest; cell widths dx / 2^level */
+    int32_t kind[6];        /* 0 as the link says, 1 coarser neighbour, 2 finer neighbours */
+    int32_t nbr[6][4];      /* kind 1: {coarse block, o1, o2, -1}; kind 2: fine blocks by half */
+} ora_amr;
+
 #define ORA_OK 0
 #define ORA_EINVAL (-1)
 #define ORA_ENONPHYS (-3)

@@ -35,6 +35,14 @@ BLOCK_DTYPE = np.dtype([("nx", "<i4"), ("ny", "<i4"), ("nz", "<i4"),
                         ("ng", "<i4"), ("offset", "<i8")])
 LINK_DTYPE = np.dtype([("nbr", "<i4", (6,))])
 
+# Refinement: a face whose link is LEVEL_FACE touches another level; the AMR
+# table says how (kind 1: one coarser block, nbr = (block, o1, o2, -1) with
+# (o1, o2) where this face starts on the coarse face, in coarse cells along
+# the two transverse axes in x, y, z order; kind 2: the 2^(ndim-1) finer
+# blocks covering the face, nbr[h1 + 2 h2] by transverse half).
+LEVEL_FACE = -3
+AMR_DTYPE = np.dtype([("level", "<i4"), ("kind", "<i4", (6,)), ("nbr", "<i4", (6, 4))])
+
 
 @dataclasses.dataclass
 class Problem:
@@ -54,6 +62,8 @@ class Problem:
     U0: np.ndarray        # float64 (nvar, ncell), NaN in all padding
     seed: Optional[int] = None
     grid: Optional[tuple] = None   # (NBx, NBy, NBz, n) for uniform block grids
+    amr: Optional[np.ndarray] = None   # AMR_DTYPE per block, for meshes with refinement levels
+    origin: Optional[np.ndarray] = None   # (nblocks, 3) lower corner of each block (AMR meshes)
 
     @property
     def nvar(self) -> int:
@@ -71,7 +81,18 @@ class Problem:
     def copy(self) -> "Problem":
         return dataclasses.replace(self, U0=self.U0.copy(),
                                    blocks=self.blocks.copy(),
-                                   links=self.links.copy())
+                                   links=self.links.copy(),
+                                   amr=None if self.amr is None else self.amr.copy())
+
+    def cell_volumes(self) -> np.ndarray:
+        """Volume (area in 2D) of every cell of one variable plane (0 in the
+        padding): dx dy dz / 2^(ndim level) per block."""
+        vol = np.zeros((1, self.ncell))
+        base = self.dx * self.dy * (self.dz if self.ndim == 3 else 1.0)
+        for b in range(self.nblocks):
+            lev = 0 if self.amr is None else int(self.amr[b]["level"])
+            interior(vol, self.blocks, b, self.ndim)[...] = base / 2.0 ** (self.ndim * lev)
+        return vol[0]
 
 
 # ----------------------------------------------------------------------------
@@ -358,6 +379,117 @@ def random_blocks(ndim, sizes, ng, seed, recon=PLM_MC, rk=2, gamma=1.4, cfl=0.8,
     return Problem("random", ndim, recon, rk, gamma, cfl, dx, dx,
                    dx if ndim == 3 else 1.0, blocks, links, ncell, 1, U, seed,
                    (NB[0], NB[1], NB[2], n))
+
+
+def amr_mesh(ndim, NBc, n, ng, refine):
+    """Two-level mesh: a periodic NBc block grid of n^ndim-cell blocks at level
+    0, where the coarse blocks at the positions in `refine` are replaced by
+    their 2^ndim children (level 1, n^ndim cells of half the width).
+
+    Returns (blocks, links, amr, origin, ncell); origin is each block's lower
+    corner in units of level-0 cells.  Block order: the unrefined coarse blocks
+    (x fastest), then the children of each refined block (x fastest).
+    """
+    NB = tuple(NBc) + (1,) * (3 - len(NBc))
+    if ndim == 2:
+        NB = (NB[0], NB[1], 1)
+    refine = {tuple(r) + (0,) * (3 - len(r)) for r in refine}
+    order = []              # (level, position in that level's block grid)
+    for K in range(NB[2]):
+        for J in range(NB[1]):
+            for I in range(NB[0]):
+                if (I, J, K) not in refine:
+                    order.append((0, (I, J, K)))
+    for (I, J, K) in sorted(refine, key=lambda q: (q[2], q[1], q[0])):
+        for c in range(2 ** ndim):
+            a, b_, e = c & 1, (c >> 1) & 1, (c >> 2) & 1
+            order.append((1, (2 * I + a, 2 * J + b_, 2 * K + e if ndim == 3 else 0)))
+    index = {key: i for i, key in enumerate(order)}
+    nz = n if ndim == 3 else 1
+    blocks, ncell = make_table([(n, n, nz)] * len(order), ng, ndim)
+    links = np.zeros(len(order), dtype=LINK_DTYPE)
+    amr = np.zeros(len(order), dtype=AMR_DTYPE)
+    amr["nbr"] = -1
+    origin = np.zeros((len(order), 3))
+    for i, (lev, pos) in enumerate(order):
+        dims = [NB[d] * 2 ** lev for d in range(3)]
+        amr[i]["level"] = lev
+        origin[i] = [pos[d] * n / 2 ** lev if d < ndim else 0.0 for d in range(3)]
+        nbr = [OUTFLOW] * 6
+        for d in range(ndim):
+            t = [e for e in range(3) if e != d]          # transverse axes, x, y, z order
+            for side, step in ((0, -1), (1, 1)):
+                f = 2 * d + side
+                q = list(pos)
+                q[d] = (q[d] + step) % dims[d]
+                if (lev, tuple(q)) in index:
+                    nb = index[(lev, tuple(q))]
+                    nbr[f] = PERIODIC_SELF if nb == i else nb
+                elif lev == 1 and (0, tuple(x // 2 for x in q)) in index:
+                    nbr[f] = LEVEL_FACE
+                    amr[i]["kind"][f] = 1
+                    amr[i]["nbr"][f] = [index[(0, tuple(x // 2 for x in q))],
+                                        (pos[t[0]] % 2) * (n // 2),
+                                        (pos[t[1]] % 2) * (n // 2) if ndim == 3 else 0, -1]
+                elif lev == 0:
+                    nbr[f] = LEVEL_FACE
+                    amr[i]["kind"][f] = 2
+                    fine = []
+                    for h in range(2 ** (ndim - 1)):
+                        r = [0, 0, 0]
+                        r[d] = 2 * q[d] + (1 if side == 0 else 0)
+                        r[t[0]] = 2 * pos[t[0]] + (h & 1)
+                        r[t[1]] = (2 * pos[t[1]] + (h >> 1)) if ndim == 3 else 0
+                        fine.append(index[(1, tuple(r))])
+                    amr[i]["nbr"][f] = fine + [-1] * (4 - len(fine))
+                else:
+                    raise ValueError("levels may differ by one across a face")
+        links[i]["nbr"] = nbr
+    return blocks, links, amr, origin, ncell
+
+
+def amr_problem(ndim, NBc=(4, 4, 4), n=8, ng=2, refine=None, seed=0, recon=PLM_MC, rk=2,
+                gamma=1.4, cfl=0.5, nsteps=5, flow="blob"):
+    """A periodic two-level mesh (see amr_mesh; by default the central
+    2^ndim coarse blocks are refined) with a smooth state: a density and
+    pressure bump moving diagonally through the refined patch ("blob"), or
+    seeded smooth random fields ("random").  dx = 1 / (NBc[0] n) at level 0."""
+    NBc = tuple(NBc[:ndim])
+    if refine is None:
+        refine = [tuple(c // 2 - 1 + a for c, a in zip(NBc, idx))
+                  for idx in np.ndindex(*(2,) * ndim)]
+    blocks, links, amr, origin, ncell = amr_mesh(ndim, NBc, n, ng, refine)
+    nb = len(blocks)
+    U = empty_state(ndim + 2, ncell)
+    L = [NBc[d] * n for d in range(ndim)]                 # domain extent in level-0 cells
+    (r,) = _streams(seed, 1)
+    modes = [(r.integers(1, 3, ndim), r.uniform(0, 2 * np.pi), r.uniform(-1, 1)) for _ in range(4)]
+    for b in range(nb):
+        lev = int(amr[b]["level"])
+        h = 1.0 / 2 ** lev
+        c = [origin[b][d] + (np.arange(n) + 0.5) * h for d in range(ndim)]     # cell centres
+        if ndim == 3:
+            X = np.meshgrid(c[0] / L[0], c[1] / L[1], c[2] / L[2], indexing="ij")
+            X = [x.transpose(2, 1, 0) for x in X]                 # (z, y, x)
+        else:
+            X = np.meshgrid(c[0] / L[0], c[1] / L[1], indexing="ij")
+            X = [x.T[None] for x in X]                            # (1, y, x)
+        if flow == "blob":
+            r2 = sum((np.minimum(np.abs(x - 0.3), 1 - np.abs(x - 0.3))) ** 2 for x in X)
+            bump = np.exp(-r2 / 0.02)
+            rho = 1.0 + 0.5 * bump
+            p = 1.0 + 0.3 * bump
+            vel = [np.full_like(rho, v) for v in (0.6, 0.4, 0.3)[:ndim]]
+        else:
+            field = lambda k: sum(a * np.sin(2 * np.pi * sum(int(m[d]) * X[d] for d in range(ndim)) + ph + k)
+                                  for m, ph, a in modes)
+            rho = np.exp(0.2 * field(0.0))
+            p = np.exp(0.2 * field(1.0))
+            vel = [0.3 * field(2.0 + d) for d in range(ndim)]
+        interior(U, blocks, b, ndim)[...] = conserved(rho, vel, p, gamma)
+    dx = 1.0 / L[0]
+    return Problem(f"amr{ndim}d", ndim, recon, rk, gamma, cfl, dx, dx, dx if ndim == 3 else 1.0,
+                   blocks, links, ncell, nsteps, U, seed, None, amr, origin)
 
 
 def config(i: int, seed: int = 0) -> Problem:
