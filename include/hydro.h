@@ -57,6 +57,7 @@ extern "C" {
 
 #define HYDRO_OUTFLOW (-1)        /* zero-gradient copy of the nearest interior cell */
 #define HYDRO_PERIODIC_SELF (-2)  /* periodic wrap onto the block itself */
+#define HYDRO_LEVEL_FACE (-3)     /* face to another refinement level (hydro_amr_t) */
 
 /* One block: interior extents, guard width, first padded cell (per plane). */
 typedef struct {
@@ -75,11 +76,41 @@ typedef struct {
     int32_t ndim;     /* 2 or 3 */
     int32_t recon;    /* HYDRO_PLM_MC (needs ng >= 2) or HYDRO_WENO5 (ng >= 3) */
     int32_t rk;       /* 2 or 3 SSP-RK stages */
-    int32_t flags;    /* reserved, 0 */
+    int32_t flags;    /* 0, or HYDRO_FLAG_LEVEL_BY_LEVEL for an AMR context */
     double gamma;     /* ratio of specific heats, > 1 */
     double cfl;       /* Courant number of the unsplit sum, > 0 */
     double dx, dy, dz;  /* cell widths (dz ignored in 2D but must be > 0) */
 } hydro_params_t;
+
+/* Refinement levels (hydro_create_amr).  Flash-X's block-structured AMR
+ * (the paper's Sec. 2.2 mesh and Sec. 4.2 flux-correction listings) with
+ * refinement ratio 2 and levels that differ by at most one across a face.
+ * Per block: its level (cell widths dx / 2^level) and, for every face whose
+ * link is HYDRO_LEVEL_FACE, what lies behind it:
+ *   kind 1: one coarser block; nbr = {block, o1, o2, -1}, where this face
+ *           starts on the coarse block's face at coarse cell (o1, o2) along the
+ *           face's two transverse axes in x, y, z order (o = 0 or half the
+ *           transverse extent; o2 = 0 in 2D);
+ *   kind 2: the 2^(ndim-1) finer blocks covering the face, nbr[h1 + 2 h2] the
+ *           one over transverse half (h1, h2).
+ * All blocks of an AMR problem share nx, ny, nz and ng; every extent is even
+ * and at least 2 ng.  Guard cells behind a coarser face take the coarse cell
+ * that contains them; behind finer faces, the pairwise sum of the 2^ndim
+ * fine cells they cover times 2^-ndim (normal pair, then first, then second
+ * transverse axis).  One dt for all levels.  After every stage each coarse
+ * cell next to a finer face is corrected by sigma b_s (dt ((Fbar - Fc)/dx)):
+ * Fc its own flux through the face, Fbar the fine fluxes through it averaged
+ * in pairs, sigma = +1 on a low face and -1 on a high one, faces in the order
+ * -x, +x, -y, +y, -z, +z.  HYDRO_FLAG_LEVEL_BY_LEVEL runs the levels finest
+ * first with their corrections in between (the paper's level-by-level
+ * listing) instead of all blocks, then all corrections (all-levels listing);
+ * both give the same result bit for bit. */
+#define HYDRO_FLAG_LEVEL_BY_LEVEL 1
+typedef struct {
+    int32_t level;
+    int32_t kind[6];      /* 0: the link says; 1: coarser block; 2: finer blocks */
+    int32_t nbr[6][4];
+} hydro_amr_t;
 
 /* Launch configuration of the stage kernels (chosen by an autotuner). */
 #define HYDRO_MODE_PERSISTENT 0  /* one launch per stage over all blocks */
@@ -117,6 +148,20 @@ int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks,
 int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks,
                  const hydro_link_t *links, int32_t nblocks, int64_t ncell_total,
                  void *stream, hydro_ctx_t **out);
+
+/* hydro_validate / hydro_create for a mesh with refinement levels (amr: one
+ * entry per block, HOST pointer, copied; see hydro_amr_t).  In an AMR context
+ * the guard layers of faces to another level are materialised in the state
+ * array of each stage input (hydro_step, hydro_rk_stage and
+ * hydro_fill_guards write them into the caller's array too), only the
+ * persistent launch mode is accepted by hydro_set_tuning, and
+ * hydro_step_vjp returns HYDRO_EINVAL. */
+int hydro_validate_amr(const hydro_params_t *params, const hydro_block_t *blocks,
+                       const hydro_link_t *links, const hydro_amr_t *amr, int32_t nblocks,
+                       int64_t ncell_total);
+int hydro_create_amr(const hydro_params_t *params, const hydro_block_t *blocks,
+                     const hydro_link_t *links, const hydro_amr_t *amr, int32_t nblocks,
+                     int64_t ncell_total, void *stream, hydro_ctx_t **out);
 
 /* Replace / read the launch configuration.  Invalidates captured graphs.
  * HYDRO_MODE_TELESCOPING is the paper's telescoping RK variant (Sec. 4.2,

@@ -18,9 +18,11 @@ HYDRO_OK, HYDRO_EINVAL, HYDRO_EHIP, HYDRO_ENONPHYS, HYDRO_ENOMEM = 0, -1, -2, -3
 MODE_PERSISTENT, MODE_PERBLOCK = 0, 1
 TILES = {0: (8, 8), 1: (16, 8), 2: (16, 16)}
 
-EXPORTS = ("hydro_validate", "hydro_create", "hydro_set_tuning", "hydro_get_tuning",
+EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create_amr",
+           "hydro_set_tuning", "hydro_get_tuning",
            "hydro_fill_guards", "hydro_cfl_dt", "hydro_rk_stage", "hydro_step",
            "hydro_step_vjp", "hydro_status", "hydro_last_error", "hydro_destroy")
+FLAG_LEVEL_BY_LEVEL = 1
 
 
 class HydroError(RuntimeError):
@@ -36,6 +38,10 @@ class Block(C.Structure):
 
 class Link(C.Structure):
     _fields_ = [("nbr", C.c_int32 * 6)]
+
+
+class Amr(C.Structure):
+    _fields_ = [("level", C.c_int32), ("kind", C.c_int32 * 6), ("nbr", (C.c_int32 * 4) * 6)]
 
 
 class Params(C.Structure):
@@ -68,6 +74,10 @@ def lib():
             "hydro_validate": (C.c_int, [C.POINTER(Params), C.POINTER(Block), C.POINTER(Link), i32, i64]),
             "hydro_create": (C.c_int, [C.POINTER(Params), C.POINTER(Block), C.POINTER(Link), i32, i64, vp,
                                        C.POINTER(vp)]),
+            "hydro_validate_amr": (C.c_int, [C.POINTER(Params), C.POINTER(Block), C.POINTER(Link),
+                                             C.POINTER(Amr), i32, i64]),
+            "hydro_create_amr": (C.c_int, [C.POINTER(Params), C.POINTER(Block), C.POINTER(Link),
+                                           C.POINTER(Amr), i32, i64, vp, C.POINTER(vp)]),
             "hydro_set_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
             "hydro_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
             "hydro_fill_guards": (C.c_int, [vp, dp]),
@@ -104,6 +114,25 @@ def tables(prob):
     return P, B, L, nb
 
 
+def amr_table(prob):
+    """ctypes level table of a problem with refinement levels, or None."""
+    amr = getattr(prob, "amr", None)
+    if amr is None:
+        return None
+    amr = np.ascontiguousarray(amr)
+    A = (Amr * max(len(amr), 1))()
+    for i, a in enumerate(amr):
+        A[i].level = int(a["level"])
+        for f in range(6):
+            A[i].kind[f] = int(a["kind"][f])
+            for h in range(4):
+                A[i].nbr[f][h] = int(a["nbr"][f][h])
+    return A
+
+
 def validate(prob) -> int:
     P, B, L, nb = tables(prob)
+    A = amr_table(prob)
+    if A is not None:
+        return lib().hydro_validate_amr(C.byref(P), B, L, A, nb, int(prob.ncell))
     return lib().hydro_validate(C.byref(P), B, L, nb, int(prob.ncell))

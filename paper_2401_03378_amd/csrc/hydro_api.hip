@@ -68,6 +68,18 @@ struct hydro_ctx {
     WorkItem *d_titems[3] = {nullptr, nullptr, nullptr};
     int ntitems[3] = {0, 0, 0};
     double *d_tbuf = nullptr;    // U^n | A | B in the thick layout
+    // refinement levels: faces to other levels, flux registers, per-level work
+    bool amr = false;
+    std::vector<hydro_amr_t> ha;
+    DevAmr *d_amr = nullptr;
+    double *d_freg = nullptr;    // register slots x nvar x nface
+    int32_t nface = 0;
+    int2 *d_afill = nullptr;     // (block, face) of every face to another level
+    int nafill = 0;
+    int2 *d_acorr = nullptr;     // (block, face) of coarse faces with finer neighbours, by face then level
+    std::vector<int> acorr_start;  // entries of face f, level L: [acorr_start[f*(nlev+1)+L], ...[+1])
+    int nlev = 1;
+    std::vector<int> lvl_first, lvl_count;   // work items of level L in the persistent list
 };
 
 namespace {
@@ -141,12 +153,74 @@ std::string check_problem(const hydro_params_t *p, const hydro_block_t *blocks, 
     return "";
 }
 
+// A mesh with refinement levels: the same-level checks on the links with
+// every face to another level taken as outflow, then the level table.
+std::string check_amr(const hydro_params_t *p, const hydro_block_t *blocks, const hydro_link_t *links,
+                      const hydro_amr_t *amr, int32_t nblocks, int64_t ncell)
+{
+    if (!p) return "null params";
+    if (nblocks > 0 && (!blocks || !links || !amr)) return "null descriptor table";
+    if (p->flags & ~HYDRO_FLAG_LEVEL_BY_LEVEL) return "unknown flags";
+    const int nd = p->ndim;
+    std::vector<hydro_link_t> same(links, links + std::max(0, nblocks));
+    for (int b = 0; b < nblocks; ++b)
+        for (int f = 0; f < 6; ++f) {
+            const bool level_face = (f < 2 * nd) && amr[b].kind[f] != 0;
+            if ((links[b].nbr[f] == HYDRO_LEVEL_FACE) != level_face)
+                return "block " + std::to_string(b) + ": link and level table disagree";
+            if (level_face) same[b].nbr[f] = HYDRO_OUTFLOW;
+        }
+    hydro_params_t q = *p;
+    q.flags = 0;
+    std::string why = check_problem(&q, blocks, same.data(), nblocks, ncell);
+    if (!why.empty()) return why;
+    for (int b = 0; b < nblocks; ++b) {
+        const hydro_block_t &B = blocks[b];
+        if (B.nx != blocks[0].nx || B.ny != blocks[0].ny || B.nz != blocks[0].nz || B.ng != blocks[0].ng)
+            return "blocks of an AMR mesh must share nx, ny, nz and ng";
+        for (int d = 0; d < nd; ++d)
+            if (extent(B, d) % 2 != 0 || extent(B, d) < 2 * B.ng)
+                return "block " + std::to_string(b) + ": extents must be even and at least 2 ng";
+        if (amr[b].level < 0 || amr[b].level > 20) return "block " + std::to_string(b) + ": level out of range";
+    }
+    for (int b = 0; b < nblocks; ++b)
+        for (int d = 0; d < nd; ++d) {
+            const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
+            const int h1n = extent(blocks[b], o1) / 2, h2n = (nd == 3) ? extent(blocks[b], o2) / 2 : 0;
+            for (int side = 0; side < 2; ++side) {
+                const int f = 2 * d + side, opp = 2 * d + 1 - side;
+                const std::string at = "block " + std::to_string(b) + " face " + std::to_string(f) + ": ";
+                const int kind = amr[b].kind[f];
+                if (kind == 1) {
+                    const int cb = amr[b].nbr[f][0], q1 = amr[b].nbr[f][1], q2 = amr[b].nbr[f][2];
+                    if (cb < 0 || cb >= nblocks) return at + "coarser block out of range";
+                    if (amr[cb].level != amr[b].level - 1 || amr[cb].kind[opp] != 2) return at + "coarser block does not match";
+                    if (!(q1 == 0 || q1 == h1n) || !((nd == 2) ? q2 == 0 : (q2 == 0 || q2 == h2n)))
+                        return at + "face offset not a half face";
+                    const int h = q1 / h1n + 2 * ((nd == 3) ? q2 / h2n : 0);
+                    if (amr[cb].nbr[opp][h] != b) return at + "coarser block does not list this block";
+                } else if (kind == 2) {
+                    for (int h = 0; h < (1 << (nd - 1)); ++h) {
+                        const int fb = amr[b].nbr[f][h];
+                        if (fb < 0 || fb >= nblocks) return at + "finer block out of range";
+                        if (amr[fb].level != amr[b].level + 1 || amr[fb].kind[opp] != 1 || amr[fb].nbr[opp][0] != b ||
+                            amr[fb].nbr[opp][1] != (h & 1) * h1n || amr[fb].nbr[opp][2] != (h >> 1) * h2n)
+                            return at + "finer block does not match";
+                    }
+                } else if (kind != 0) {
+                    return at + "unknown kind";
+                }
+            }
+        }
+    return "";
+}
+
 // Host tables: geometry and, per face, the source of its guard layers.
 void build_tables(hydro_ctx *c)
 {
     const int nd = c->prm.ndim;
     c->h_dev.resize(c->nblocks);
-    c->h_faces.assign((size_t)c->nblocks * 6, FaceSrc{0, 0, 0, 0, 0});
+    c->h_faces.assign((size_t)c->nblocks * 6, FaceSrc{0, 0, 0, 0, 0, -1, 0});
     for (int b = 0; b < c->nblocks; ++b) {
         const hydro_block_t &B = c->hb[b];
         DevBlock D{};
@@ -155,8 +229,10 @@ void build_tables(hydro_ctx *c)
         D.px = B.nx + 2 * B.ng;
         D.py = B.ny + 2 * B.ng;
         D.gz = (nd == 3) ? B.ng : 0;
+        D.lev = c->amr ? c->ha[b].level : 0;
         c->h_dev[b] = D;
     }
+    int slot = 0;
     for (int b = 0; b < c->nblocks; ++b) {
         const hydro_block_t &B = c->hb[b];
         for (int d = 0; d < nd; ++d)
@@ -164,11 +240,16 @@ void build_tables(hydro_ctx *c)
                 const int nb = c->hl[b].nbr[2 * d + side];
                 const int n = extent(B, d);
                 FaceSrc f{};
+                f.reg = -1;
                 const hydro_block_t &S = (nb >= 0) ? c->hb[nb] : B;
                 f.off = S.offset;
                 f.px = S.nx + 2 * S.ng;
                 f.py = S.ny + 2 * S.ng;
-                if (nb == HYDRO_OUTFLOW) {           // nearest interior cell
+                if (nb == HYDRO_LEVEL_FACE) {        // another level: the block's own (filled) guard layers
+                    f.A = 0;
+                    f.B = 1;
+                    f.reg = slot++;
+                } else if (nb == HYDRO_OUTFLOW) {    // nearest interior cell
                     f.A = (side == 0) ? 0 : n - 1;
                     f.B = 0;
                 } else {                             // neighbour or periodic: distance l-1 from the face
@@ -219,6 +300,19 @@ void build_items(hydro_ctx *c, std::vector<WorkItem> &list, std::vector<WorkItem
     start[c->nblocks] = (int)perblock.size();
     list = perblock;
     std::stable_sort(list.begin(), list.end(), [](const WorkItem &a, const WorkItem &b) { return a.cost > b.cost; });
+    if (c->amr) {
+        // levels finest first, each level's items largest first
+        std::stable_sort(list.begin(), list.end(), [c](const WorkItem &a, const WorkItem &b) {
+            return c->ha[a.block].level > c->ha[b.block].level;
+        });
+        c->lvl_first.assign(c->nlev, 0);
+        c->lvl_count.assign(c->nlev, 0);
+        for (size_t q = 0; q < list.size(); ++q) {
+            const int L = c->ha[list[q].block].level;
+            if (c->lvl_count[L]++ == 0) c->lvl_first[L] = (int)q;
+        }
+        return;
+    }
     if (c->tune.xcd) {
         // deal blocks round-robin onto 8 lanes, keep each lane's items in
         // order, then interleave the lanes position by position
@@ -316,7 +410,55 @@ StageArgs stage_args(hydro_ctx *c, int s, const double *dt, const double *Un, co
     a.Us = Us;
     a.Uout = Uout;
     a.nbad = c->d_nbad;
+    a.freg = c->d_freg;
+    a.nface = c->nface;
     return a;
+}
+
+AmrArgs amr_args(hydro_ctx *c, double *U)
+{
+    AmrArgs g{};
+    g.blocks = c->d_blocks;
+    g.amr = c->d_amr;
+    g.faces = c->d_faces;
+    g.nc = c->ncell;
+    g.nface = c->nface;
+    g.idx = 1.0 / c->prm.dx;
+    g.idy = 1.0 / c->prm.dy;
+    g.idz = 1.0 / c->prm.dz;
+    g.freg = c->d_freg;
+    g.U = U;
+    return g;
+}
+
+// Guard layers of faces to another level, from the interiors of U.
+int enqueue_amr_fill(hydro_ctx *c, double *U, hipStream_t st)
+{
+    AmrArgs g = amr_args(c, U);
+    g.list = c->d_afill;
+    g.nlist = c->nafill;
+    hipError_t e = launch_amr_fill(g, c->prm.ndim, st);
+    if (e != hipSuccess) return hip_fail(c, e, "level guard launch");
+    return HYDRO_OK;
+}
+
+// Flux corrections of stage s on Uout, face by face in the order -x .. +z,
+// for the coarse blocks of levels [l0, l1).
+int enqueue_amr_correct(hydro_ctx *c, int s, const double *dt, double *Uout, int l0, int l1, hipStream_t st)
+{
+    AmrArgs g = amr_args(c, Uout);
+    double a;
+    rk_coeffs(c->prm.rk, s, a, g.b);
+    g.dt = dt;
+    for (int f = 0; f < 2 * c->prm.ndim; ++f) {
+        const int lo = c->acorr_start[(size_t)f * (c->nlev + 1) + l0];
+        const int hi = c->acorr_start[(size_t)f * (c->nlev + 1) + l1];
+        g.list = c->d_acorr + lo;
+        g.nlist = hi - lo;
+        hipError_t e = launch_amr_correct(g, c->prm.ndim, st);
+        if (e != hipSuccess) return hip_fail(c, e, "flux correction launch");
+    }
+    return HYDRO_OK;
 }
 
 int persistent_grid(hydro_ctx *c)
@@ -375,6 +517,24 @@ int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const
             if (e != hipSuccess) return hip_fail(c, e, "stage launch");
         }
         return HYDRO_OK;
+    }
+    if (c->amr) {
+        int rc = enqueue_amr_fill(c, const_cast<double *>(Us), st);
+        if (rc) return rc;
+        if (c->prm.flags & HYDRO_FLAG_LEVEL_BY_LEVEL) {
+            for (int L = c->nlev - 1; L >= 0; --L) {
+                a.items = c->d_items + c->lvl_first[L];
+                a.nitems = c->lvl_count[L];
+                const int grid = c->tune.grid > 0 ? std::min(c->tune.grid, a.nitems) : a.nitems;
+                hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, c->tune.variant, true, grid, st);
+                if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+                if ((rc = enqueue_amr_correct(c, s, dt, Uout, L, L + 1, st))) return rc;
+            }
+            return HYDRO_OK;
+        }
+        hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, c->tune.variant, true, persistent_grid(c), st);
+        if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+        return enqueue_amr_correct(c, s, dt, Uout, 0, c->nlev, st);
     }
     hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, c->tune.variant, true, persistent_grid(c), st);
     if (e != hipSuccess) return hip_fail(c, e, "stage launch");
@@ -540,7 +700,7 @@ int setup_tele(hydro_ctx *c)
     }
     c->ncell_t = off;
     c->ngt = ngt;
-    std::vector<FaceSrc> tf((size_t)c->nblocks * 6, FaceSrc{0, 0, 0, 0, 0});
+    std::vector<FaceSrc> tf((size_t)c->nblocks * 6, FaceSrc{0, 0, 0, 0, 0, -1, 0});
     for (int b = 0; b < c->nblocks; ++b)
         for (int d = 0; d < nd; ++d)
             for (int side = 0; side < 2; ++side) {
@@ -548,6 +708,7 @@ int setup_tele(hydro_ctx *c)
                 const int n = extent(c->hb[b], d);
                 const int src = (nb >= 0) ? nb : b;
                 FaceSrc f{};
+                f.reg = -1;
                 f.off = tb[src].off;
                 f.px = tb[src].px;
                 f.py = tb[src].py;
@@ -662,6 +823,58 @@ int enqueue_step_tele(hydro_ctx *c, double *U, double *dt, int compute_dt, hipSt
     return HYDRO_OK;
 }
 
+// Device tables of a mesh with refinement levels: the level table, flux
+// registers for every face to another level, the list of those faces (guard
+// fill) and the coarse faces with finer neighbours by face and level
+// (correction).  Returns non-zero with c->err set on failure.
+int setup_amr(hydro_ctx *c)
+{
+    const int nd = c->prm.ndim;
+    int nslots = 0;
+    for (const FaceSrc &f : c->h_faces) nslots += (f.reg >= 0);
+    c->nface = 1;
+    if (c->nblocks > 0) {
+        const hydro_block_t &B = c->hb[0];
+        c->nface = std::max(B.ny * B.nz, B.nx * B.nz);
+        if (nd == 3) c->nface = std::max(c->nface, B.nx * B.ny);
+        if (nd == 2) c->nface = std::max(B.nx, B.ny);
+    }
+    std::vector<DevAmr> da(std::max(1, c->nblocks));
+    std::vector<int2> fill;
+    for (int b = 0; b < c->nblocks; ++b) {
+        for (int f = 0; f < 6; ++f) {
+            da[b].kind[f] = c->ha[b].kind[f];
+            for (int h = 0; h < 4; ++h) da[b].nbr[f][h] = c->ha[b].nbr[f][h];
+            if (f < 2 * nd && c->ha[b].kind[f] != 0) fill.push_back(make_int2(b, f));
+        }
+    }
+    std::vector<int2> corr;
+    c->acorr_start.assign((size_t)6 * (c->nlev + 1), 0);
+    for (int f = 0; f < 6; ++f)
+        for (int L = 0; L <= c->nlev; ++L) {
+            c->acorr_start[(size_t)f * (c->nlev + 1) + L] = (int)corr.size();
+            if (L == c->nlev || f >= 2 * nd) continue;
+            for (int b = 0; b < c->nblocks; ++b)
+                if (c->ha[b].level == L && c->ha[b].kind[f] == 2) corr.push_back(make_int2(b, f));
+        }
+    c->nafill = (int)fill.size();
+    const size_t regs = (size_t)std::max(1, nslots) * c->nv * c->nface;
+    if (hipMalloc(&c->d_amr, sizeof(DevAmr) * da.size()) != hipSuccess ||
+        hipMalloc(&c->d_freg, sizeof(double) * regs) != hipSuccess ||
+        hipMalloc(&c->d_afill, sizeof(int2) * std::max<size_t>(1, fill.size())) != hipSuccess ||
+        hipMalloc(&c->d_acorr, sizeof(int2) * std::max<size_t>(1, corr.size())) != hipSuccess) {
+        c->err = "device tables (levels)";
+        return 1;
+    }
+    if (hipMemcpy(c->d_amr, da.data(), sizeof(DevAmr) * da.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (!fill.empty() && hipMemcpy(c->d_afill, fill.data(), sizeof(int2) * fill.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!corr.empty() && hipMemcpy(c->d_acorr, corr.data(), sizeof(int2) * corr.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+        c->err = "level table upload";
+        return 1;
+    }
+    return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -674,12 +887,19 @@ int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks, co
 
 static thread_local std::string g_create_err;
 
-int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
-                 int32_t nblocks, int64_t ncell_total, void *stream, hydro_ctx_t **out)
+int hydro_validate_amr(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
+                       const hydro_amr_t *amr, int32_t nblocks, int64_t ncell_total)
+{
+    return check_amr(params, blocks, links, amr, nblocks, ncell_total).empty() ? HYDRO_OK : HYDRO_EINVAL;
+}
+
+static int create_ctx(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
+                      const hydro_amr_t *amr, int32_t nblocks, int64_t ncell_total, void *stream, hydro_ctx_t **out)
 {
     if (!out) return HYDRO_EINVAL;
     *out = nullptr;
-    std::string why = check_problem(params, blocks, links, nblocks, ncell_total);
+    std::string why = amr ? check_amr(params, blocks, links, amr, nblocks, ncell_total)
+                          : check_problem(params, blocks, links, nblocks, ncell_total);
     if (!why.empty()) {
         g_create_err = why;
         return HYDRO_EINVAL;
@@ -692,6 +912,11 @@ int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks, cons
     c->hb.assign(blocks, blocks + nblocks);
     c->hl.assign(links, links + nblocks);
     c->stream = (hipStream_t)stream;
+    if (amr) {
+        c->amr = true;
+        c->ha.assign(amr, amr + nblocks);
+        for (int b = 0; b < nblocks; ++b) c->nlev = std::max(c->nlev, amr[b].level + 1);
+    }
     auto bail = [&](int code) {
         g_create_err = c->err;
         hydro_destroy(c);
@@ -743,10 +968,30 @@ int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks, cons
     c->tune.use_graph = 1;
     c->tune.xcd = 0;
     c->tune.variant = 0;
+    if (c->amr) {
+        if (setup_amr(c)) return bail(c->err.rfind("device", 0) == 0 ? HYDRO_ENOMEM : HYDRO_EHIP);
+    }
     int rc = upload_items(c);
     if (rc) return bail(rc);
     *out = c;
     return HYDRO_OK;
+}
+
+int hydro_create(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
+                 int32_t nblocks, int64_t ncell_total, void *stream, hydro_ctx_t **out)
+{
+    return create_ctx(params, blocks, links, nullptr, nblocks, ncell_total, stream, out);
+}
+
+int hydro_create_amr(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
+                     const hydro_amr_t *amr, int32_t nblocks, int64_t ncell_total, void *stream, hydro_ctx_t **out)
+{
+    if (!amr && nblocks > 0) {
+        g_create_err = "null level table";
+        return HYDRO_EINVAL;
+    }
+    hydro_amr_t none{};
+    return create_ctx(params, blocks, links, amr ? amr : &none, nblocks, ncell_total, stream, out);
 }
 
 int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
@@ -757,6 +1002,8 @@ int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
     if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0 || t->variant < 0 || t->variant > 1 ||
         t->xcd < 0 || t->xcd > 2)
         return fail(c, HYDRO_EINVAL, "tuning range");
+    if (c->amr && t->mode != HYDRO_MODE_PERSISTENT)
+        return fail(c, HYDRO_EINVAL, "a mesh with refinement levels runs in the persistent mode only");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     const int old_tile = c->tune.tile;
@@ -784,7 +1031,9 @@ int hydro_get_tuning(hydro_ctx_t *c, hydro_tuning_t *t)
 int hydro_fill_guards(hydro_ctx_t *c, double *U)
 {
     if (!c || !U) return HYDRO_EINVAL;
-    return enqueue_guards(c, U, 0, c->nblocks, c->stream);
+    int rc = enqueue_guards(c, U, 0, c->nblocks, c->stream);
+    if (rc || !c->amr) return rc;
+    return enqueue_amr_fill(c, U, c->stream);
 }
 
 int hydro_cfl_dt(hydro_ctx_t *c, const double *U, double *dt_dev)
@@ -853,6 +1102,7 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
     if (gUn == gUnext) return fail(c, HYDRO_EINVAL, "gUn aliases gUnext");
     if (c->tune.mode == HYDRO_MODE_TELESCOPING)
         return fail(c, HYDRO_EINVAL, "the adjoint is defined for the per-stage-fill step only");
+    if (c->amr) return fail(c, HYDRO_EINVAL, "the adjoint is defined on meshes without refinement levels");
     if (c->nitems == 0) return HYDRO_OK;
     int rc = setup_vjp(c);
     if (rc) return rc;
@@ -948,6 +1198,10 @@ void hydro_destroy(hydro_ctx_t *c)
     (void)hipFree(c->d_lines);
     (void)hipFree(c->d_citems);
     (void)hipFree(c->d_xitems);
+    (void)hipFree(c->d_amr);
+    (void)hipFree(c->d_freg);
+    (void)hipFree(c->d_afill);
+    (void)hipFree(c->d_acorr);
     (void)hipFree(c->d_inc_start);
     (void)hipFree(c->d_inc);
     free_tele(c);

@@ -22,16 +22,26 @@ struct DevBlock {
     int32_t nx, ny, nz, ng;
     int32_t px, py;         // padded x and y extents
     int32_t gz;             // z guard width (ng in 3D, 0 in 2D)
-    int32_t pad;
+    int32_t lev;            // refinement level: cell widths dx / 2^lev
 };
 
 // Where the guard layers of one block face are gathered from: the source
 // block's padded geometry and the map pos -> A + B*pos of the coordinate
-// along the face normal (neighbour interior, periodic wrap, or outflow copy).
+// along the face normal (neighbour interior, periodic wrap, or outflow copy;
+// on a face to another refinement level, the block's own guard layers).
+// reg >= 0: the fluxes through this face go to flux-register slot reg.
 struct FaceSrc {
     int64_t off;
     int32_t px, py;
     int32_t A, B;
+    int32_t reg, pad;
+};
+
+// A block's faces to other refinement levels: kind 1, one coarser block,
+// nbr = {block, o1, o2, -1}; kind 2, the finer blocks, nbr[h1 + 2 h2].
+struct DevAmr {
+    int32_t kind[6];
+    int32_t nbr[6][4];
 };
 
 // A work item: an xy tile of one block over a range of z planes.

@@ -54,6 +54,19 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
         const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
         const int z0 = it.z & 0xffff, nzc = it.z >> 16;
         const int wx = min(TX, B.nx - x0), wy = min(TY, B.ny - y0);
+        // inverse cell widths of this block's level (exact power-of-two scaling)
+        const double lsc = (double)(1 << B.lev);
+        const double idxb = A.idx * lsc, idyb = A.idy * lsc, idzb = A.idz * lsc;
+        // flux through block face f at transverse cell (e1, e2) to its register slot, if any
+        auto reg_put = [&](int f, int e1, int e2, const double (&Fv)[5]) {
+            if (A.freg == nullptr) return;
+            const int slot = F6[f].reg;
+            if (slot < 0) return;
+            const int n1 = (f < 2) ? B.ny : B.nx;
+            double *r = A.freg + (int64_t)slot * NV * A.nface + (int64_t)e2 * n1 + e1;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) r[(int64_t)v * A.nface] = Fv[v];
+        };
         const bool own = (tx < wx) && (ty < wy);
         const int i = x0 + tx, j = y0 + ty;
         const int nhalo = 2 * H * (wx + wy);
@@ -117,6 +130,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 recon_cell<NDIM, RECON>(s0, qa, qpz);      // cell z0-1: keep its right face
                 recon_cell<NDIM, RECON>(s1, qm, qb);       // cell z0
                 bad |= hllc<NDIM, 2>(qpz, qm, Flo, K);
+                if (z0 == 0) reg_put(4, i, j, Flo);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qpz[v] = qb[v];
 #pragma unroll
@@ -163,6 +177,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                     double qm[5], qp[5], Fhi[5];
                     recon_cell<NDIM, RECON>(zw, qm, qp);   // cell k+1
                     bad |= hllc<NDIM, 2>(qpz, qm, Fhi, K);
+                    if (k == B.nz - 1) reg_put(5, i, j, Fhi);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) { Dz[v] = Fhi[v] - Flo[v]; Flo[v] = Fhi[v]; }
 #pragma unroll
@@ -287,11 +302,13 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 bad |= hllc<NDIM, 0>(WL, qmx, Fv, K);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) sFx[v][ty][tx] = Fv[v];
+                if (i == 0) reg_put(0, j, (NDIM == 3) ? k : 0, Fv);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) WL[v] = sQy[v][ty][tx];
                 bad |= hllc<NDIM, 1>(WL, qmy, Fv, K);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) sFy[v][ty][tx] = Fv[v];
+                if (j == 0) reg_put(2, i, (NDIM == 3) ? k : 0, Fv);
             }
             if (etype == 1) {
                 double WL[5], Fv[5];
@@ -300,6 +317,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 bad |= hllc<NDIM, 0>(WL, qme, Fv, K);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) sFx[v][epos][wx] = Fv[v];
+                if (x0 + wx == B.nx) reg_put(1, y0 + epos, (NDIM == 3) ? k : 0, Fv);
             } else if (etype == 3) {
                 double WL[5], Fv[5];
 #pragma unroll
@@ -307,6 +325,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 bad |= hllc<NDIM, 1>(WL, qme, Fv, K);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) sFy[v][wy][epos] = Fv[v];
+                if (y0 + wy == B.ny) reg_put(3, x0 + epos, (NDIM == 3) ? k : 0, Fv);
             }
             __syncthreads();
 
@@ -317,8 +336,8 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 for (int v = 0; v < NV; ++v) {
                     const double Dx = sFx[v][ty][tx + 1] - sFx[v][ty][tx];
                     const double Dy = sFy[v][ty + 1][tx] - sFy[v][ty][tx];
-                    double acc = Dx * A.idx + Dy * A.idy;
-                    if constexpr (NDIM == 3) acc = acc + Dz[v] * A.idz;
+                    double acc = Dx * idxb + Dy * idyb;
+                    if constexpr (NDIM == 3) acc = acc + Dz[v] * idzb;
                     const double L = -acc;
                     const double T = fma(dt, L, cus[v]);
                     double out;
@@ -365,6 +384,8 @@ __global__ void __launch_bounds__(TX *TY) k_cfl_partial(CflArgs A)
         const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
         const int z0 = it.z & 0xffff, nzc = it.z >> 16;
         const int i = x0 + tx, j = y0 + ty;
+        const double lsc = (double)(1 << B.lev);
+        const double idxb = A.idx * lsc, idyb = A.idy * lsc, idzb = A.idz * lsc;
         if (i < B.nx && j < B.ny) {
             for (int k = z0; k < z0 + nzc; ++k) {
                 double u[5], wv[5];
@@ -372,8 +393,8 @@ __global__ void __launch_bounds__(TX *TY) k_cfl_partial(CflArgs A)
                 bad |= eos<NDIM>(u, wv, A.g1);
                 const double r = 1.0 / u[0];
                 const double c = sqrt((A.gamma * wv[4]) * r);
-                double sig = ((fabs(wv[1]) + c) * A.idx) + ((fabs(wv[2]) + c) * A.idy);
-                if constexpr (NDIM == 3) sig = sig + ((fabs(wv[3]) + c) * A.idz);
+                double sig = ((fabs(wv[1]) + c) * idxb) + ((fabs(wv[2]) + c) * idyb);
+                if constexpr (NDIM == 3) sig = sig + ((fabs(wv[3]) + c) * idzb);
                 m = (sig > m) ? sig : m;
             }
         }
@@ -407,6 +428,123 @@ __global__ void __launch_bounds__(256) k_cfl_final(const double *__restrict__ pa
     if (tid == 0) {
         for (int q = 1; q < 4; ++q) m = (red[q] > m) ? red[q] : m;
         *dt = cfl / m;
+    }
+}
+
+// Guard layers of faces to another refinement level (ratio 2), one
+// workgroup per (block, face) of the list.  Behind a coarser neighbour a
+// guard cell takes the coarse cell containing it; behind finer neighbours it
+// takes the 2^NDIM fine cells it covers, summed in pairs (the normal pair,
+// then along the first and the second transverse axis) times 2^-NDIM.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_amr_fill(AmrArgs A)
+{
+    constexpr int NV = NDIM + 2;
+    const int64_t nc = A.nc;
+    for (int w = blockIdx.x; w < A.nlist; w += gridDim.x) {
+        const int b = A.list[w].x, f = A.list[w].y;
+        const int d = f >> 1, side = f & 1;
+        const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
+        const DevBlock B = A.blocks[b];
+        const DevAmr &M = A.amr[b];
+        const int ext[3] = {B.nx, B.ny, B.nz};
+        const int n = ext[d], n1 = ext[o1], n2 = (NDIM == 3) ? ext[o2] : 1;
+        const int total = B.ng * n1 * n2;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            const int e1 = t % n1, e2 = (t / n1) % n2, l = 1 + t / (n1 * n2);
+            int g[3] = {0, 0, 0};
+            g[d] = (side == 0) ? -l : n - 1 + l;
+            g[o1] = e1;
+            if (NDIM == 3) g[o2] = e2;
+            const int64_t gi = cell_at(B, g[0], g[1], g[2]);
+            if (M.kind[f] == 1) {
+                const DevBlock C = A.blocks[M.nbr[f][0]];
+                const int cext[3] = {C.nx, C.ny, C.nz};
+                const int half = (l + 1) / 2;
+                int s[3] = {0, 0, 0};
+                s[d] = (side == 0) ? cext[d] - half : half - 1;
+                s[o1] = M.nbr[f][1] + e1 / 2;
+                if (NDIM == 3) s[o2] = M.nbr[f][2] + e2 / 2;
+                const int64_t si = cell_at(C, s[0], s[1], s[2]);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) A.U[v * nc + gi] = A.U[v * nc + si];
+            } else {
+                const int h1n = n1 / 2, h2n = (NDIM == 3) ? n2 / 2 : 1;
+                const int h1 = e1 / h1n, h2 = (NDIM == 3) ? e2 / h2n : 0;
+                const DevBlock F = A.blocks[M.nbr[f][h1 + 2 * h2]];
+                const int fext[3] = {F.nx, F.ny, F.nz};
+                const int p0 = (side == 0) ? fext[d] - 2 * l : 2 * (l - 1);
+                const int f1 = 2 * (e1 - h1 * h1n), f2 = (NDIM == 3) ? 2 * (e2 - h2 * h2n) : 0;
+                auto fine = [&](int v, int in, int i1, int i2) {
+                    int s[3] = {0, 0, 0};
+                    s[d] = p0 + in;
+                    s[o1] = f1 + i1;
+                    if (NDIM == 3) s[o2] = f2 + i2;
+                    return A.U[v * nc + cell_at(F, s[0], s[1], s[2])];
+                };
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double val;
+                    if constexpr (NDIM == 3)
+                        val = (((fine(v, 0, 0, 0) + fine(v, 1, 0, 0)) + (fine(v, 0, 1, 0) + fine(v, 1, 1, 0))) +
+                               ((fine(v, 0, 0, 1) + fine(v, 1, 0, 1)) + (fine(v, 0, 1, 1) + fine(v, 1, 1, 1)))) * 0.125;
+                    else
+                        val = ((fine(v, 0, 0, 0) + fine(v, 1, 0, 0)) + (fine(v, 0, 1, 0) + fine(v, 1, 1, 0))) * 0.25;
+                    A.U[v * nc + gi] = val;
+                }
+            }
+        }
+    }
+}
+
+// Flux correction at the finer side of coarse blocks, one workgroup per
+// (coarse block, face) of the list (all for one face direction and side, so
+// no cell is touched twice in a launch): the coarse cell next to the face
+// gets sigma b (dt ((Fbar - Fc) / dx)), Fbar the fine fluxes through the face
+// averaged in pairs, Fc its own flux, sigma = +1 on a low and -1 on a high face.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_amr_correct(AmrArgs A)
+{
+    constexpr int NV = NDIM + 2;
+    const int64_t nc = A.nc;
+    const double dt = *A.dt;
+    for (int w = blockIdx.x; w < A.nlist; w += gridDim.x) {
+        const int b = A.list[w].x, f = A.list[w].y;
+        const int d = f >> 1, side = f & 1;
+        const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
+        const DevBlock B = A.blocks[b];
+        const DevAmr &M = A.amr[b];
+        const int ext[3] = {B.nx, B.ny, B.nz};
+        const int n = ext[d], n1 = ext[o1], n2 = (NDIM == 3) ? ext[o2] : 1;
+        const double lsc = (double)(1 << B.lev);
+        const double id = ((d == 0) ? A.idx : ((d == 1) ? A.idy : A.idz)) * lsc;
+        const int ff = 2 * d + 1 - side;                  // the fine blocks' face
+        const double *Rc = A.freg + (int64_t)A.faces[6 * (int64_t)b + f].reg * NV * A.nface;
+        for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+            const int e1 = t % n1, e2 = t / n1;
+            const int h1n = n1 / 2, h2n = (NDIM == 3) ? n2 / 2 : 1;
+            const int h1 = e1 / h1n, h2 = (NDIM == 3) ? e2 / h2n : 0;
+            const int fb = M.nbr[f][h1 + 2 * h2];
+            const int f1 = 2 * (e1 - h1 * h1n), f2 = (NDIM == 3) ? 2 * (e2 - h2 * h2n) : 0;
+            const double *Rf = A.freg + (int64_t)A.faces[6 * (int64_t)fb + ff].reg * NV * A.nface;
+            int c[3] = {0, 0, 0};
+            c[d] = (side == 0) ? 0 : n - 1;
+            c[o1] = e1;
+            if (NDIM == 3) c[o2] = e2;
+            const int64_t ci = cell_at(B, c[0], c[1], c[2]);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double *rf = Rf + (int64_t)v * A.nface;
+                double Fbar;
+                if constexpr (NDIM == 3)
+                    Fbar = ((rf[f2 * n1 + f1] + rf[f2 * n1 + f1 + 1]) + (rf[(f2 + 1) * n1 + f1] + rf[(f2 + 1) * n1 + f1 + 1])) * 0.25;
+                else
+                    Fbar = (rf[f1] + rf[f1 + 1]) * 0.5;
+                const double Fc = Rc[(int64_t)v * A.nface + e2 * n1 + e1];
+                const double corr = A.b * (dt * ((Fbar - Fc) * id));
+                A.U[v * nc + ci] = (side == 0) ? A.U[v * nc + ci] + corr : A.U[v * nc + ci] - corr;
+            }
+        }
     }
 }
 
@@ -587,6 +725,22 @@ hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_
         k_fill_guards<3><<<nblk * 6, 256, 0, st>>>(a);
     else
         k_fill_guards<2><<<nblk * 4, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_fill(const AmrArgs &a, int ndim, hipStream_t st)
+{
+    if (a.nlist <= 0) return hipSuccess;
+    if (ndim == 3) k_amr_fill<3><<<a.nlist, 256, 0, st>>>(a);
+    else k_amr_fill<2><<<a.nlist, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_correct(const AmrArgs &a, int ndim, hipStream_t st)
+{
+    if (a.nlist <= 0) return hipSuccess;
+    if (ndim == 3) k_amr_correct<3><<<a.nlist, 256, 0, st>>>(a);
+    else k_amr_correct<2><<<a.nlist, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -19,6 +19,24 @@ struct StageArgs {
     const double *Us;
     double *Uout;
     unsigned long long *nbad;
+    double *freg;               // flux registers (faces with FaceSrc::reg >= 0)
+    int32_t nface;              // cells per register slot and variable
+};
+
+// Coarse-fine faces: guard fill across levels and the flux correction.
+struct AmrArgs {
+    const DevBlock *blocks;
+    const DevAmr *amr;
+    const FaceSrc *faces;
+    const int2 *list;           // fill: (block, face); correction: (block, face)
+    int32_t nlist;
+    int64_t nc;
+    int32_t nface;
+    double idx, idy, idz;
+    double b;                   // stage coefficient of the correction
+    const double *dt;
+    const double *freg;
+    double *U;                  // state whose guards are filled / stage output corrected
 };
 
 struct CflArgs {
@@ -84,6 +102,8 @@ hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl
 hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_fill(const TeleArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick, hipStream_t st);
+hipError_t launch_amr_fill(const AmrArgs &a, int ndim, hipStream_t st);
+hipError_t launch_amr_correct(const AmrArgs &a, int ndim, hipStream_t st);
 hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t st);
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int nitems, hipStream_t st);
 hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st);

@@ -23,7 +23,7 @@ class Solver:
     blocks, links, ncell).  State tensors are float64 (nvar, ncell) on the
     solver's device."""
 
-    def __init__(self, prob, device="cuda", stream=None, tuning=None):
+    def __init__(self, prob, device="cuda", stream=None, tuning=None, level_by_level=False):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the hydro step runs only in its HIP kernels")
         self.prob = prob
@@ -33,10 +33,16 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._L = _hip.lib()
         P, B, L, nb = _hip.tables(prob)
+        A = _hip.amr_table(prob)
         ctx = C.c_void_p()
         with torch.cuda.device(self.device):
-            rc = self._L.hydro_create(C.byref(P), B, L, nb, self.ncell,
-                                      C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+            if A is None:
+                rc = self._L.hydro_create(C.byref(P), B, L, nb, self.ncell,
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+            else:
+                P.flags = _hip.FLAG_LEVEL_BY_LEVEL if level_by_level else 0
+                rc = self._L.hydro_create_amr(C.byref(P), B, L, A, nb, self.ncell,
+                                              C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         if rc != _hip.HYDRO_OK:
             raise HydroError(rc, self._L.hydro_last_error(None).decode())
         self.ctx = ctx

@@ -71,3 +71,27 @@ def test_validate_mismatched_faces_and_weno_guards():
     assert _hip.validate(p) == _hip.HYDRO_EINVAL
     q = W.random_blocks(3, 6, 2, seed=0, recon=W.WENO5, rk=3)
     assert _hip.validate(q) == _hip.HYDRO_EINVAL
+
+
+def test_validate_amr_meshes_and_broken_tables():
+    """Host-only check of a mesh with refinement levels: generated meshes
+    pass; a link that disagrees with the level table, a level gap, a wrong
+    half-face offset and a plain hydro_validate of the same links fail."""
+    from paper_2401_03378_amd import workloads as W
+    for ndim, ng, recon in ((2, 2, 0), (3, 3, 1)):
+        p = W.amr_problem(ndim, n=8, ng=ng, recon=recon, rk=2)
+        assert _hip.validate(p) == _hip.HYDRO_OK
+        plain = p.copy()
+        plain.amr = None
+        assert _hip.validate(plain) == _hip.HYDRO_EINVAL         # LEVEL_FACE links need the table
+        i = int(np.flatnonzero(p.amr["kind"][:, 3] == 2)[0])
+        q = p.copy()
+        q.links[i]["nbr"][3] = 0
+        assert _hip.validate(q) == _hip.HYDRO_EINVAL
+        q = p.copy()
+        q.amr[i]["level"] = 1
+        assert _hip.validate(q) == _hip.HYDRO_EINVAL
+        j = int(np.flatnonzero(p.amr["kind"][:, 2] == 1)[0])
+        q = p.copy()
+        q.amr[j]["nbr"][2][1] = 1
+        assert _hip.validate(q) == _hip.HYDRO_EINVAL
