@@ -104,6 +104,40 @@ def extras(S, prob, U0, ms_per_step):
             "speedup_vs_perblock": round(tpb * 1e3 / ms_per_step, 2)}
 
 
+def amr_extra(nsteps=10):
+    """A two-level mesh: 8^3 coarse blocks of 16^3 cells with the central
+    4^3 refined (448 coarse + 512 fine blocks, 3.9 M zones), WENO5 + HLLC +
+    SSP-RK3, the density/pressure blob crossing the coarse-fine faces; zone
+    updates per second of hydro_step (coarse-fine guard fill, stage, flux
+    correction), with the all-levels and the level-by-level order."""
+    import torch
+    from paper_2401_03378_amd import workloads as W
+    from paper_2401_03378_amd.solver import Solver
+    prob = W.amr_problem(3, NBc=(8, 8, 8), n=16, ng=3, recon=W.WENO5, rk=3, flow="blob",
+                         refine=[(i, j, k) for i in range(2, 6) for j in range(2, 6) for k in range(2, 6)])
+    zones = prob.interior_zones
+    res = {"workload": "two-level mesh: 448 coarse + 512 fine blocks of 16^3 (central 4^3 coarse blocks refined), "
+                       "WENO5 + HLLC + SSP-RK3, flux correction at coarse-fine faces",
+           "zones": zones}
+    for lbl in (False, True):
+        S = Solver(prob, level_by_level=lbl)
+        U0 = S.to_device(prob.U0)
+        U = U0.clone()
+        for _ in range(3):
+            S.step(U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            S.step(U)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / nsteps
+        S.status()
+        key = "level_by_level" if lbl else "all_levels"
+        res[key] = {"ms_per_step": round(t * 1e3, 4), "zone_updates_per_s": zones * prob.rk / t}
+        S.close()
+    return {"amr": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,12 +147,17 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=10, help="steps timed per stage launch with events")
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 512 MiB device copy")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--amr-only", action="store_true",
+                    help="only time the two-level AMR workload (prints its JSON object)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint/forward and per-block-launch comparisons")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the step runs on one GPU (blocks are not sharded across GPUs); --gpus must be 1"}))
         sys.exit(2)
+    if args.amr_only:
+        print(json.dumps(amr_extra(args.steps)), flush=True)
+        return
 
     import torch
     from paper_2401_03378_amd import workloads as W
@@ -226,6 +265,7 @@ def main():
     }
     if not args.no_extras:
         out.update(extras(S, prob, U0, ms_per_step))
+        out.update(amr_extra())
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(W.config(1), args.cpu_budget)
     S.close()

@@ -76,8 +76,8 @@ struct hydro_ctx {
     int32_t nface = 0;
     int2 *d_afill = nullptr;     // (block, face) of every face to another level
     int nafill = 0;
-    int2 *d_acorr = nullptr;     // (block, face) of coarse faces with finer neighbours, by face then level
-    std::vector<int> acorr_start;  // entries of face f, level L: [acorr_start[f*(nlev+1)+L], ...[+1])
+    int2 *d_acorr = nullptr;     // (block, 0) of the blocks with faces to finer neighbours, by level
+    std::vector<int> acorr_start;  // blocks of level L: [acorr_start[L], acorr_start[L + 1])
     int nlev = 1;
     std::vector<int> lvl_first, lvl_count;   // work items of level L in the persistent list
 };
@@ -422,6 +422,7 @@ AmrArgs amr_args(hydro_ctx *c, double *U)
     g.amr = c->d_amr;
     g.faces = c->d_faces;
     g.nc = c->ncell;
+    g.ng = (c->nblocks > 0) ? c->hb[0].ng : 1;
     g.nface = c->nface;
     g.idx = 1.0 / c->prm.dx;
     g.idy = 1.0 / c->prm.dy;
@@ -442,22 +443,18 @@ int enqueue_amr_fill(hydro_ctx *c, double *U, hipStream_t st)
     return HYDRO_OK;
 }
 
-// Flux corrections of stage s on Uout, face by face in the order -x .. +z,
-// for the coarse blocks of levels [l0, l1).
+// Flux corrections of stage s on Uout for the coarse blocks of levels
+// [l0, l1) (each block's faces in the order -x .. +z).
 int enqueue_amr_correct(hydro_ctx *c, int s, const double *dt, double *Uout, int l0, int l1, hipStream_t st)
 {
     AmrArgs g = amr_args(c, Uout);
     double a;
     rk_coeffs(c->prm.rk, s, a, g.b);
     g.dt = dt;
-    for (int f = 0; f < 2 * c->prm.ndim; ++f) {
-        const int lo = c->acorr_start[(size_t)f * (c->nlev + 1) + l0];
-        const int hi = c->acorr_start[(size_t)f * (c->nlev + 1) + l1];
-        g.list = c->d_acorr + lo;
-        g.nlist = hi - lo;
-        hipError_t e = launch_amr_correct(g, c->prm.ndim, st);
-        if (e != hipSuccess) return hip_fail(c, e, "flux correction launch");
-    }
+    g.list = c->d_acorr + c->acorr_start[l0];
+    g.nlist = c->acorr_start[l1] - c->acorr_start[l0];
+    hipError_t e = launch_amr_correct(g, c->prm.ndim, st);
+    if (e != hipSuccess) return hip_fail(c, e, "flux correction launch");
     return HYDRO_OK;
 }
 
@@ -849,14 +846,16 @@ int setup_amr(hydro_ctx *c)
         }
     }
     std::vector<int2> corr;
-    c->acorr_start.assign((size_t)6 * (c->nlev + 1), 0);
-    for (int f = 0; f < 6; ++f)
-        for (int L = 0; L <= c->nlev; ++L) {
-            c->acorr_start[(size_t)f * (c->nlev + 1) + L] = (int)corr.size();
-            if (L == c->nlev || f >= 2 * nd) continue;
-            for (int b = 0; b < c->nblocks; ++b)
-                if (c->ha[b].level == L && c->ha[b].kind[f] == 2) corr.push_back(make_int2(b, f));
+    c->acorr_start.assign((size_t)c->nlev + 1, 0);
+    for (int L = 0; L <= c->nlev; ++L) {
+        c->acorr_start[L] = (int)corr.size();
+        if (L == c->nlev) continue;
+        for (int b = 0; b < c->nblocks; ++b) {
+            bool finer = false;
+            for (int f = 0; f < 2 * nd; ++f) finer |= (c->ha[b].kind[f] == 2);
+            if (c->ha[b].level == L && finer) corr.push_back(make_int2(b, 0));
         }
+    }
     c->nafill = (int)fill.size();
     const size_t regs = (size_t)std::max(1, nslots) * c->nv * c->nface;
     if (hipMalloc(&c->d_amr, sizeof(DevAmr) * da.size()) != hipSuccess ||

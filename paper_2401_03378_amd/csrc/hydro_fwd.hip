@@ -441,17 +441,18 @@ __global__ void __launch_bounds__(256) k_amr_fill(AmrArgs A)
 {
     constexpr int NV = NDIM + 2;
     const int64_t nc = A.nc;
-    for (int w = blockIdx.x; w < A.nlist; w += gridDim.x) {
-        const int b = A.list[w].x, f = A.list[w].y;
+    // one workgroup per (face of the list, guard layer l = 1 .. ng)
+    for (int w = blockIdx.x; w < A.nlist * A.ng; w += gridDim.x) {
+        const int b = A.list[w / A.ng].x, f = A.list[w / A.ng].y;
+        const int l = 1 + w % A.ng;
         const int d = f >> 1, side = f & 1;
         const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
         const DevBlock B = A.blocks[b];
         const DevAmr &M = A.amr[b];
         const int ext[3] = {B.nx, B.ny, B.nz};
         const int n = ext[d], n1 = ext[o1], n2 = (NDIM == 3) ? ext[o2] : 1;
-        const int total = B.ng * n1 * n2;
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            const int e1 = t % n1, e2 = (t / n1) % n2, l = 1 + t / (n1 * n2);
+        for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+            const int e1 = t % n1, e2 = t / n1;
             int g[3] = {0, 0, 0};
             g[d] = (side == 0) ? -l : n - 1 + l;
             g[o1] = e1;
@@ -497,11 +498,12 @@ __global__ void __launch_bounds__(256) k_amr_fill(AmrArgs A)
     }
 }
 
-// Flux correction at the finer side of coarse blocks, one workgroup per
-// (coarse block, face) of the list (all for one face direction and side, so
-// no cell is touched twice in a launch): the coarse cell next to the face
-// gets sigma b (dt ((Fbar - Fc) / dx)), Fbar the fine fluxes through the face
-// averaged in pairs, Fc its own flux, sigma = +1 on a low and -1 on a high face.
+// Flux correction of the coarse blocks of the list, one workgroup per block:
+// faces with finer neighbours in the order -x, +x, -y, +y, -z, +z (a barrier
+// between faces, so a cell next to two of them takes its corrections in that
+// order); the coarse cell next to a face gets sigma b (dt ((Fbar - Fc) / dx)),
+// Fbar the fine fluxes through the face averaged in pairs, Fc its own flux,
+// sigma = +1 on a low and -1 on a high face.
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_amr_correct(AmrArgs A)
 {
@@ -509,41 +511,45 @@ __global__ void __launch_bounds__(256) k_amr_correct(AmrArgs A)
     const int64_t nc = A.nc;
     const double dt = *A.dt;
     for (int w = blockIdx.x; w < A.nlist; w += gridDim.x) {
-        const int b = A.list[w].x, f = A.list[w].y;
-        const int d = f >> 1, side = f & 1;
-        const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
+        const int b = A.list[w].x;
         const DevBlock B = A.blocks[b];
         const DevAmr &M = A.amr[b];
         const int ext[3] = {B.nx, B.ny, B.nz};
-        const int n = ext[d], n1 = ext[o1], n2 = (NDIM == 3) ? ext[o2] : 1;
         const double lsc = (double)(1 << B.lev);
-        const double id = ((d == 0) ? A.idx : ((d == 1) ? A.idy : A.idz)) * lsc;
-        const int ff = 2 * d + 1 - side;                  // the fine blocks' face
-        const double *Rc = A.freg + (int64_t)A.faces[6 * (int64_t)b + f].reg * NV * A.nface;
-        for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
-            const int e1 = t % n1, e2 = t / n1;
-            const int h1n = n1 / 2, h2n = (NDIM == 3) ? n2 / 2 : 1;
-            const int h1 = e1 / h1n, h2 = (NDIM == 3) ? e2 / h2n : 0;
-            const int fb = M.nbr[f][h1 + 2 * h2];
-            const int f1 = 2 * (e1 - h1 * h1n), f2 = (NDIM == 3) ? 2 * (e2 - h2 * h2n) : 0;
-            const double *Rf = A.freg + (int64_t)A.faces[6 * (int64_t)fb + ff].reg * NV * A.nface;
-            int c[3] = {0, 0, 0};
-            c[d] = (side == 0) ? 0 : n - 1;
-            c[o1] = e1;
-            if (NDIM == 3) c[o2] = e2;
-            const int64_t ci = cell_at(B, c[0], c[1], c[2]);
+        for (int f = 0; f < 2 * NDIM; ++f) {
+            if (M.kind[f] != 2) continue;
+            const int d = f >> 1, side = f & 1;
+            const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
+            const int n = ext[d], n1 = ext[o1], n2 = (NDIM == 3) ? ext[o2] : 1;
+            const double id = ((d == 0) ? A.idx : ((d == 1) ? A.idy : A.idz)) * lsc;
+            const int ff = 2 * d + 1 - side;              // the fine blocks' face
+            const double *Rc = A.freg + (int64_t)A.faces[6 * (int64_t)b + f].reg * NV * A.nface;
+            for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
+                const int e1 = t % n1, e2 = t / n1;
+                const int h1n = n1 / 2, h2n = (NDIM == 3) ? n2 / 2 : 1;
+                const int h1 = e1 / h1n, h2 = (NDIM == 3) ? e2 / h2n : 0;
+                const int fb = M.nbr[f][h1 + 2 * h2];
+                const int f1 = 2 * (e1 - h1 * h1n), f2 = (NDIM == 3) ? 2 * (e2 - h2 * h2n) : 0;
+                const double *Rf = A.freg + (int64_t)A.faces[6 * (int64_t)fb + ff].reg * NV * A.nface;
+                int c[3] = {0, 0, 0};
+                c[d] = (side == 0) ? 0 : n - 1;
+                c[o1] = e1;
+                if (NDIM == 3) c[o2] = e2;
+                const int64_t ci = cell_at(B, c[0], c[1], c[2]);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double *rf = Rf + (int64_t)v * A.nface;
-                double Fbar;
-                if constexpr (NDIM == 3)
-                    Fbar = ((rf[f2 * n1 + f1] + rf[f2 * n1 + f1 + 1]) + (rf[(f2 + 1) * n1 + f1] + rf[(f2 + 1) * n1 + f1 + 1])) * 0.25;
-                else
-                    Fbar = (rf[f1] + rf[f1 + 1]) * 0.5;
-                const double Fc = Rc[(int64_t)v * A.nface + e2 * n1 + e1];
-                const double corr = A.b * (dt * ((Fbar - Fc) * id));
-                A.U[v * nc + ci] = (side == 0) ? A.U[v * nc + ci] + corr : A.U[v * nc + ci] - corr;
+                for (int v = 0; v < NV; ++v) {
+                    const double *rf = Rf + (int64_t)v * A.nface;
+                    double Fbar;
+                    if constexpr (NDIM == 3)
+                        Fbar = ((rf[f2 * n1 + f1] + rf[f2 * n1 + f1 + 1]) + (rf[(f2 + 1) * n1 + f1] + rf[(f2 + 1) * n1 + f1 + 1])) * 0.25;
+                    else
+                        Fbar = (rf[f1] + rf[f1 + 1]) * 0.5;
+                    const double Fc = Rc[(int64_t)v * A.nface + e2 * n1 + e1];
+                    const double corr = A.b * (dt * ((Fbar - Fc) * id));
+                    A.U[v * nc + ci] = (side == 0) ? A.U[v * nc + ci] + corr : A.U[v * nc + ci] - corr;
+                }
             }
+            __syncthreads();
         }
     }
 }
@@ -731,8 +737,8 @@ hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_
 hipError_t launch_amr_fill(const AmrArgs &a, int ndim, hipStream_t st)
 {
     if (a.nlist <= 0) return hipSuccess;
-    if (ndim == 3) k_amr_fill<3><<<a.nlist, 256, 0, st>>>(a);
-    else k_amr_fill<2><<<a.nlist, 256, 0, st>>>(a);
+    if (ndim == 3) k_amr_fill<3><<<a.nlist * a.ng, 256, 0, st>>>(a);
+    else k_amr_fill<2><<<a.nlist * a.ng, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -28,8 +28,9 @@ struct AmrArgs {
     const DevBlock *blocks;
     const DevAmr *amr;
     const FaceSrc *faces;
-    const int2 *list;           // fill: (block, face); correction: (block, face)
+    const int2 *list;           // fill: (block, face); correction: (block, -)
     int32_t nlist;
+    int32_t ng;                 // guard layers (shared by all blocks of a mesh with levels)
     int64_t nc;
     int32_t nface;
     double idx, idy, idz;
