@@ -2,6 +2,7 @@
 // device tables, the work-item list, stage buffers, the SSP-RK step driver
 // and its hipGraph replay.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -230,6 +231,9 @@ void build_tables(hydro_ctx *c)
         D.py = B.ny + 2 * B.ng;
         D.gz = (nd == 3) ? B.ng : 0;
         D.lev = c->amr ? c->ha[b].level : 0;
+        D.ix = std::ldexp(1.0 / c->prm.dx, D.lev);
+        D.iy = std::ldexp(1.0 / c->prm.dy, D.lev);
+        D.iz = std::ldexp(1.0 / c->prm.dz, D.lev);
         c->h_dev[b] = D;
     }
     int slot = 0;
@@ -692,6 +696,9 @@ int setup_tele(hydro_ctx *c)
         D.px = B.nx + 2 * ngt;
         D.py = B.ny + 2 * ngt;
         D.gz = (nd == 3) ? ngt : 0;
+        D.ix = 1.0 / c->prm.dx;
+        D.iy = 1.0 / c->prm.dy;
+        D.iz = 1.0 / c->prm.dz;
         tb[b] = D;
         off += (int64_t)D.px * D.py * ((nd == 3) ? B.nz + 2 * ngt : 1);
     }

@@ -23,6 +23,7 @@ struct DevBlock {
     int32_t px, py;         // padded x and y extents
     int32_t gz;             // z guard width (ng in 3D, 0 in 2D)
     int32_t lev;            // refinement level: cell widths dx / 2^lev
+    double ix, iy, iz;      // inverse cell widths of the level: (1/dx) 2^lev (exact scaling)
 };
 
 // Where the guard layers of one block face are gathered from: the source

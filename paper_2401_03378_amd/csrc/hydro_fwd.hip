@@ -25,7 +25,7 @@
 
 namespace hydro {
 
-template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF>
+template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF, bool LV = false>
 __device__ __forceinline__ void stage_body(const StageArgs &A)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
@@ -54,12 +54,11 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
         const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
         const int z0 = it.z & 0xffff, nzc = it.z >> 16;
         const int wx = min(TX, B.nx - x0), wy = min(TY, B.ny - y0);
-        // inverse cell widths of this block's level (exact power-of-two scaling)
-        const double lsc = (double)(1 << B.lev);
-        const double idxb = A.idx * lsc, idyb = A.idy * lsc, idzb = A.idz * lsc;
+        // inverse cell widths: this block's level on a mesh with levels
+        const double idxb = LV ? B.ix : A.idx, idyb = LV ? B.iy : A.idy, idzb = LV ? B.iz : A.idz;
         // flux through block face f at transverse cell (e1, e2) to its register slot, if any
         auto reg_put = [&](int f, int e1, int e2, const double (&Fv)[5]) {
-            if (A.freg == nullptr) return;
+            if constexpr (!LV) return;       // meshes without levels keep no face fluxes
             const int slot = F6[f].reg;
             if (slot < 0) return;
             const int n1 = (f < 2) ? B.ny : B.nx;
@@ -368,6 +367,14 @@ __global__ void __launch_bounds__(TX *TY) k_stage_pf(StageArgs A)
     stage_body<NDIM, RECON, TX, TY, GATHER, true>(A);
 }
 
+// Meshes with refinement levels: the plain schedule that also writes the
+// fluxes through faces to another level into their flux registers.
+template <int NDIM, int RECON, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))) k_stage_lv(StageArgs A)
+{
+    stage_body<NDIM, RECON, TX, TY, true, false, true>(A);
+}
+
 // Per-workgroup maximum of the unsplit wave-speed sum over the interior
 // cells of its work items.
 template <int NDIM, int TX, int TY>
@@ -384,8 +391,7 @@ __global__ void __launch_bounds__(TX *TY) k_cfl_partial(CflArgs A)
         const int x0 = it.xy & 0xffff, y0 = it.xy >> 16;
         const int z0 = it.z & 0xffff, nzc = it.z >> 16;
         const int i = x0 + tx, j = y0 + ty;
-        const double lsc = (double)(1 << B.lev);
-        const double idxb = A.idx * lsc, idyb = A.idy * lsc, idzb = A.idz * lsc;
+        const double idxb = B.ix, idyb = B.iy, idzb = B.iz;
         if (i < B.nx && j < B.ny) {
             for (int k = z0; k < z0 + nzc; ++k) {
                 double u[5], wv[5];
@@ -515,13 +521,12 @@ __global__ void __launch_bounds__(256) k_amr_correct(AmrArgs A)
         const DevBlock B = A.blocks[b];
         const DevAmr &M = A.amr[b];
         const int ext[3] = {B.nx, B.ny, B.nz};
-        const double lsc = (double)(1 << B.lev);
         for (int f = 0; f < 2 * NDIM; ++f) {
             if (M.kind[f] != 2) continue;
             const int d = f >> 1, side = f & 1;
             const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
             const int n = ext[d], n1 = ext[o1], n2 = (NDIM == 3) ? ext[o2] : 1;
-            const double id = ((d == 0) ? A.idx : ((d == 1) ? A.idy : A.idz)) * lsc;
+            const double id = (d == 0) ? B.ix : ((d == 1) ? B.iy : B.iz);
             const int ff = 2 * d + 1 - side;              // the fine blocks' face
             const double *Rc = A.freg + (int64_t)A.faces[6 * (int64_t)b + f].reg * NV * A.nface;
             for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
@@ -670,6 +675,12 @@ hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick
 template <int NDIM, int RECON, int TX, int TY, bool GATHER>
 static hipError_t launch_stage_t(const StageArgs &a, int variant, int grid, hipStream_t st)
 {
+    if constexpr (GATHER) {
+        if (a.freg != nullptr) {
+            k_stage_lv<NDIM, RECON, TX, TY><<<grid, TX * TY, 0, st>>>(a);
+            return hipGetLastError();
+        }
+    }
     if (variant == 1)
         k_stage_pf<NDIM, RECON, TX, TY, GATHER><<<grid, TX * TY, 0, st>>>(a);
     else
