@@ -16,6 +16,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -39,9 +40,14 @@ def log(*a):
 
 
 def source_hash():
+    """Hash of the stage kernel's code (comments and layout ignored), to
+    tell whether counter records were taken on the kernel as it is."""
     h = hashlib.sha256()
     for f in ("hydro_fwd.hip", "hydro_common.h"):
-        h.update(open(os.path.join(ROOT, "paper_2401_03378_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2401_03378_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -9,6 +9,12 @@
 //  k_fill_guards  materialised guard fill (the listing's fill_guardcells)
 //               for callers that want guards in the array, and for the
 //               plain per-block launch form.
+//  k_stage_lv, k_amr_fill, k_amr_correct  meshes with refinement levels
+//               (the paper's flux-correction listings, Sec. 4.2): the stage
+//               kernel that also writes the fluxes through faces to another
+//               level into flux registers, the guard layers of those faces,
+//               and the correction of the coarse cells next to finer faces.
+//  k_tele_*     thick block copies of the telescoping step.
 //
 // Work decomposition of k_stage.  A work item is an xy tile (TX x TY cells)
 // of one block over a run of z planes.  The workgroup marches through the
@@ -19,8 +25,9 @@
 // primitives; x and y reconstruction read their stencils from there.  Guard
 // cells are never read from the state array: a halo cell outside the block
 // is gathered from the cell it is a copy of (neighbour interior, periodic
-// wrap, outflow copy).  A persistent grid walks the work list with a fixed
-// stride.
+// wrap, outflow copy); only the guard layers of faces to another refinement
+// level are read from the array, after k_amr_fill has written them.  A
+// persistent grid walks the work list with a fixed stride.
 #include "hydro_kernels.h"
 
 namespace hydro {
