@@ -1,6 +1,7 @@
 // C ABI of the FP64 Euler step (declared in include/hydro.h): validation,
 // device tables, the work-item list, stage buffers, the SSP-RK step driver
-// and its hipGraph replay.
+// and its hipGraph replay, the telescoping step, meshes with refinement
+// levels (coarse-fine guard fill and flux correction) and the step VJP.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>

@@ -381,14 +381,15 @@ def random_blocks(ndim, sizes, ng, seed, recon=PLM_MC, rk=2, gamma=1.4, cfl=0.8,
                    (NB[0], NB[1], NB[2], n))
 
 
-def amr_mesh(ndim, NBc, n, ng, refine):
+def amr_mesh(ndim, NBc, n, ng, refine, bc="periodic"):
     """Two-level mesh: a periodic NBc block grid of n^ndim-cell blocks at level
     0, where the coarse blocks at the positions in `refine` are replaced by
     their 2^ndim children (level 1, n^ndim cells of half the width).
 
     Returns (blocks, links, amr, origin, ncell); origin is each block's lower
     corner in units of level-0 cells.  Block order: the unrefined coarse blocks
-    (x fastest), then the children of each refined block (x fastest).
+    (x fastest), then the children of each refined block (x fastest).  bc:
+    'periodic' (the block grid wraps) or 'outflow' on the domain faces.
     """
     NB = tuple(NBc) + (1,) * (3 - len(NBc))
     if ndim == 2:
@@ -421,7 +422,12 @@ def amr_mesh(ndim, NBc, n, ng, refine):
             for side, step in ((0, -1), (1, 1)):
                 f = 2 * d + side
                 q = list(pos)
-                q[d] = (q[d] + step) % dims[d]
+                q[d] = q[d] + step
+                if not 0 <= q[d] < dims[d]:
+                    if bc == "outflow":
+                        nbr[f] = OUTFLOW
+                        continue
+                    q[d] %= dims[d]
                 if (lev, tuple(q)) in index:
                     nb = index[(lev, tuple(q))]
                     nbr[f] = PERIODIC_SELF if nb == i else nb
@@ -449,21 +455,37 @@ def amr_mesh(ndim, NBc, n, ng, refine):
 
 
 def amr_problem(ndim, NBc=(4, 4, 4), n=8, ng=2, refine=None, seed=0, recon=PLM_MC, rk=2,
-                gamma=1.4, cfl=0.5, nsteps=5, flow="blob"):
-    """A periodic two-level mesh (see amr_mesh; by default the central
-    2^ndim coarse blocks are refined) with a smooth state: a density and
-    pressure bump moving diagonally through the refined patch ("blob"), or
-    seeded smooth random fields ("random").  dx = 1 / (NBc[0] n) at level 0."""
+                gamma=1.4, cfl=0.5, nsteps=5, flow="blob", bc=None):
+    """A two-level mesh (see amr_mesh; by default the central 2^ndim coarse
+    blocks are refined) with a smooth state: a density and pressure bump
+    moving diagonally through the refined patch ("blob"), seeded smooth random
+    fields ("random"), both periodic; or a Sedov-like blast at the domain
+    centre, inside the refined patch, with outflow faces ("blast": rho = 1,
+    p = 1e-5, total energy 1 spread over the level-0 cell volume within 3.5
+    level-0 cells of the centre).  dx = 1 / (NBc[0] n) at level 0."""
     NBc = tuple(NBc[:ndim])
     if refine is None:
         refine = [tuple(c // 2 - 1 + a for c, a in zip(NBc, idx))
                   for idx in np.ndindex(*(2,) * ndim)]
-    blocks, links, amr, origin, ncell = amr_mesh(ndim, NBc, n, ng, refine)
+    if bc is None:
+        bc = "outflow" if flow == "blast" else "periodic"
+    blocks, links, amr, origin, ncell = amr_mesh(ndim, NBc, n, ng, refine, bc)
     nb = len(blocks)
     U = empty_state(ndim + 2, ncell)
     L = [NBc[d] * n for d in range(ndim)]                 # domain extent in level-0 cells
     (r,) = _streams(seed, 1)
     modes = [(r.integers(1, 3, ndim), r.uniform(0, 2 * np.pi), r.uniform(-1, 1)) for _ in range(4)]
+    dx0 = 1.0 / L[0]
+    if flow == "blast":
+        # volume (physical units) of the cells whose centres lie in the deposit
+        blast_volume = 0.0
+        for b in range(nb):
+            lev = int(amr[b]["level"])
+            h = 1.0 / 2 ** lev
+            c = [origin[b][d] + (np.arange(n) + 0.5) * h for d in range(ndim)]
+            g = np.meshgrid(*c, indexing="ij")
+            r2 = sum((gg - 0.5 * L[0]) ** 2 for gg in g)
+            blast_volume += np.count_nonzero(r2 < 3.5 ** 2) * (h * dx0) ** ndim
     for b in range(nb):
         lev = int(amr[b]["level"])
         h = 1.0 / 2 ** lev
@@ -474,6 +496,18 @@ def amr_problem(ndim, NBc=(4, 4, 4), n=8, ng=2, refine=None, seed=0, recon=PLM_M
         else:
             X = np.meshgrid(c[0] / L[0], c[1] / L[1], indexing="ij")
             X = [x.T[None] for x in X]                            # (1, y, x)
+        if flow == "blast":
+            r2 = sum(((x - 0.5) * L[0]) ** 2 for x in X)          # in level-0 cells (cubic domain)
+            hot = r2 < 3.5 ** 2
+            rho = np.ones_like(r2)
+            p = np.full_like(r2, 1e-5)
+            vel = [np.zeros_like(r2) for _ in range(ndim)]
+            U_b = conserved(rho, vel, p, gamma)
+            # energy density making the deposit's total 1 over its volume
+            vol0 = blast_volume
+            U_b[-1] = np.where(hot, U_b[-1] + 1.0 / vol0, U_b[-1])
+            interior(U, blocks, b, ndim)[...] = U_b
+            continue
         if flow == "blob":
             r2 = sum((np.minimum(np.abs(x - 0.3), 1 - np.abs(x - 0.3))) ** 2 for x in X)
             bump = np.exp(-r2 / 0.02)

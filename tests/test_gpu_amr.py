@@ -104,3 +104,22 @@ def test_amr_refusals():
             S.set_tuning(mode=mode)
         assert e.value.code == HYDRO_EINVAL
     S.close()
+
+
+@pytest.mark.parametrize("ndim,recon,rk,n,ng", [(2, 0, 2, 8, 2), (3, 1, 3, 8, 3)])
+def test_amr_blast_with_outflow_faces(ndim, recon, rk, n, ng):
+    """A Sedov-like blast inside the refined patch, outflow on the domain
+    faces: the shock crosses the coarse-fine faces (strong jumps, positivity
+    fallback) within a few steps."""
+    p = W.amr_problem(ndim, NBc=(4, 4, 4), n=n, ng=ng, recon=recon, rk=rk, flow="blast")
+    Uo = p.U0.copy()
+    dto = O.amr_run(p, Uo, 6)
+    for lbl in (False, True):
+        S = _solver(p, level_by_level=lbl)
+        U = S.to_device(p.U0)
+        dtg = S.run(U, 6).cpu().numpy()
+        S.status()
+        np.testing.assert_array_equal(dtg, np.array(dto))
+        m = W.interior_mask(p.blocks, p.ncell, ndim)
+        assert np.array_equal(U.cpu().numpy()[:, m], Uo[:, m])
+        S.close()
