@@ -176,3 +176,39 @@ def test_refining_everything_is_the_fine_uniform_step():
     for b in range(p.nblocks):
         I, J = (int(round(p.origin[b][a_] * 2 / 8)) for a_ in range(2))
         assert np.array_equal(W.interior(a, p.blocks, b, 2), W.interior(U, q.blocks, J * 4 + I, 2))
+
+
+@pytest.mark.parametrize("recon,rk,nsteps", [(0, 2, 5), (1, 3, 2)])
+def test_refined_patch_equals_the_fine_uniform_grid(recon, rk, nsteps):
+    """A blast inside a refined patch, before its disturbance (grown by the
+    stencil reach every stage) gets near the coarse-fine faces: the fine
+    blocks' states equal those of a uniform grid of the fine width bit for
+    bit (same dt: the CFL maximum lies in the blast), so the level scaling,
+    the guard fill and the correction leave a locally uniform-grid
+    computation untouched."""
+    ng = 3 if recon == 1 else 2
+    p = W.amr_problem(2, NBc=(8, 8), n=8, ng=ng, recon=recon, rk=rk, flow="blast",
+                      refine=[(i, j) for i in range(2, 6) for j in range(2, 6)])
+    q = W.random_blocks(2, 8, ng, seed=0, recon=recon, rk=rk, bc="outflow", NB=(16, 16, 1), cfl=p.cfl)
+    q.dx = q.dy = p.dx / 2
+    # uniform grid: the blast's fine cells where the patch is, the quiet state elsewhere
+    quiet = np.array([1.0, 0.0, 0.0, 1e-5 / (p.gamma - 1.0)])
+    U = q.U0.copy()
+    for b in range(q.nblocks):
+        W.interior(U, q.blocks, b, 2)[...] = quiet[:, None, None, None]
+    where = {}
+    for b in range(p.nblocks):
+        if p.amr[b]["level"] == 1:
+            I, J = (int(round(p.origin[b][a] * 2 / 8)) for a in range(2))
+            where[b] = J * 16 + I
+            W.interior(U, q.blocks, where[b], 2)[...] = W.interior(p.U0, p.blocks, b, 2)
+    a = p.U0.copy()
+    da = O.amr_run(p, a, nsteps)
+    db = O.run(q, U, nsteps)
+    assert da == db
+    moved = 0
+    for b, qb in where.items():
+        fa, fb = W.interior(a, p.blocks, b, 2), W.interior(U, q.blocks, qb, 2)
+        assert np.array_equal(fa, fb), b
+        moved += int(np.any(fa != quiet[:, None, None, None]))
+    assert moved >= 4          # the blast has spread over several fine blocks
