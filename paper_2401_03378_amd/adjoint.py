@@ -120,3 +120,53 @@ def hydro_step(U, dt, solver):
 
 def hydro_rollout(U0, solver, nsteps, k):
     return HydroRollout.apply(U0, solver, nsteps, k)
+
+
+def time_rollouts(cases=((3, 50, 10), (1, 20, 5), (4, 10, 5))):
+    """Cost of the checkpointed adjoint against the forward rollout, for
+    (workload index, steps, checkpoint interval) cases; one JSON line each."""
+    import json
+    import time
+
+    from . import autotune
+    from . import workloads as W
+    from .solver import Solver
+
+    out = []
+    for ci, nsteps, k in cases:
+        p = W.config(ci)
+        S = Solver(p)
+        autotune.tuned_or_search(S, p, log=lambda *a: None)
+        st = TorchStepper(S)
+        U0 = S.to_device(p.U0)
+        # warm-up rollout of the same shape (graph capture, VJP scratch, allocator)
+        UN, tape = rollout(st, U0, nsteps, k)
+        rollout_vjp(st, tape, torch.nan_to_num(UN).clone())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        UN, tape = rollout(st, U0, nsteps, nsteps + 1)   # forward only (one checkpoint)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        UN, tape = rollout(st, U0, nsteps, k)
+        rollout_vjp(st, tape, torch.nan_to_num(UN).clone())
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        dt = tape.dts[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            S.step_vjp(U0, torch.nan_to_num(U0), dt)
+        torch.cuda.synchronize()
+        tv = (time.perf_counter() - t0) / 3
+        S.status()
+        r = dict(cfg=ci, name=p.name, nsteps=nsteps, k=k, t_forward_s=tf, t_fwd_plus_ckpt_bwd_s=tb,
+                 adjoint_over_forward=tb / tf, t_step_vjp_s=tv, t_step_fwd_s=tf / nsteps)
+        print(json.dumps(r), flush=True)
+        out.append(r)
+        S.close()
+    return out
+
+
+if __name__ == "__main__":
+    time_rollouts()

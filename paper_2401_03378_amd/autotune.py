@@ -124,3 +124,41 @@ def tuned_or_search(S, prob, log=print, cache=None):
     except OSError:
         pass
     return best
+
+
+def compare_forms(indices, log=print):
+    """For each named workload: the tuned persistent form (searched, or taken
+    from the cache) against the plain per-block launch form, as JSON lines."""
+    from . import workloads as W
+    from .solver import Solver
+
+    def timeit(S, U0, nsteps, warm):
+        U = U0.clone()
+        for _ in range(warm):
+            S.step(U)
+        t = _time_steps(S, U, nsteps)
+        S.status()
+        return t
+
+    out = []
+    for ci in indices:
+        p = W.config(ci)
+        S = Solver(p)
+        best = tuned_or_search(S, p, log=log)
+        U0 = S.to_device(p.U0)
+        t_best = timeit(S, U0, 5, 2)
+        S.set_tuning(mode=1, use_graph=0)
+        t_pb = timeit(S, U0, 2 if ci in (2, 4) else 5, 1)
+        z = p.interior_zones * p.rk
+        r = dict(cfg=ci, name=p.name, tuned=best, ms_step_tuned=t_best * 1e3, ms_step_perblock=t_pb * 1e3,
+                 speedup=t_pb / t_best, zus_tuned=z / t_best, zus_perblock=z / t_pb)
+        print(json.dumps(r), flush=True)
+        out.append(r)
+    return out
+
+
+if __name__ == "__main__":
+    import sys
+
+    compare_forms([int(a) for a in sys.argv[1:]] or [0, 1, 2, 3, 4],
+                  log=lambda *a: print(*a, file=sys.stderr, flush=True))

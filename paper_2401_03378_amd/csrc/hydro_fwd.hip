@@ -32,6 +32,15 @@
 
 namespace hydro {
 
+// Wave priority (0..3) for the issue arbiter of the SIMD.
+__device__ __forceinline__ void set_prio(int p)
+{
+    if (p >= 3) __builtin_amdgcn_s_setprio(3);
+    else if (p == 2) __builtin_amdgcn_s_setprio(2);
+    else if (p == 1) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF, bool LV = false>
 __device__ __forceinline__ void stage_body(const StageArgs &A)
 {
@@ -118,6 +127,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 }
             }
         };
+        if constexpr (!PF) set_prio(3);
         if constexpr (NDIM == 3) {
             if (own) {
                 double Wt[NW + 1][5];
@@ -149,16 +159,13 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
         if constexpr (PF) prefetch(z0);
         for (int kk = 0; kk < nzc; ++kk) {
             const int k = z0 + kk;
+            // Two workgroups share a CU; the arbiter favours the older one's waves,
+            // so the younger would finish last and run alone.  Lowering the
+            // priority over the last planes of an item lets a lagging
+            // co-resident workgroup catch up.
+            if constexpr (!PF) set_prio((kk < nzc - 8) ? 3 : ((kk < nzc - 4) ? 2 : ((kk < nzc - 2) ? 1 : 0)));
             double Dz[5];
             double cus[5], cun[5], chalo[NSLOT][5], cz[5];
-            if constexpr (!PF) {
-                // operands of the RK update: issued now, consumed after the plane's work
-                if (own) {
-                    const int64_t ci = cell_at(B, i, j, k);
-                    load_cons<NDIM>(A.Us, nc, ci, cus);
-                    if (A.stage != 1) load_cons<NDIM>(A.Un, nc, ci, cun);
-                }
-            }
             if constexpr (PF) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) { cus[v] = pus[v]; cun[v] = pun[v]; cz[v] = pz[v]; }
@@ -300,6 +307,16 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
             }
             __syncthreads();
 
+            if constexpr (!PF) {
+                // operands of the RK update: issued here, consumed after the Riemann
+                // problems (loaded at plane start they would hold registers through
+                // the reconstruction, where pressure peaks)
+                if (own) {
+                    const int64_t ci = cell_at(B, i, j, k);
+                    load_cons<NDIM>(A.Us, nc, ci, cus);
+                    if (A.stage != 1) load_cons<NDIM>(A.Un, nc, ci, cun);
+                }
+            }
             // Riemann problems at the faces
             if (own) {
                 double WL[5], Fv[5];
@@ -316,22 +333,32 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 for (int v = 0; v < NV; ++v) sFy[v][ty][tx] = Fv[v];
                 if (j == 0) reg_put(2, i, (NDIM == 3) ? k : 0, Fv);
             }
-            if (etype == 1) {
+            if (etype == 1 || etype == 3) {
+                // The high x and y edge faces in one pass: a y face is solved as
+                // an x face with the x and y velocity components exchanged in both
+                // states and in the flux.  The bits are the same (the only sum over
+                // these components, the kinetic energy's, starts with their pair).
+                const bool fy = (etype == 3);
+                constexpr int sx = TY * (TX + 1), sy = (TY + 1) * TX;   // per-variable strides
+                const double *ql = fy ? &sQy[0][wy][epos] : &sQx[0][epos][wx];
+                double *fo = fy ? &sFy[0][wy][epos] : &sFx[0][epos][wx];
+                const int st = fy ? sy : sx;
+                auto xch = [fy](double (&q)[5]) {
+                    const double a = q[1], b = q[2];
+                    q[1] = fy ? b : a;
+                    q[2] = fy ? a : b;
+                };
                 double WL[5], Fv[5];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) WL[v] = sQx[v][epos][wx];
+                for (int v = 0; v < 5; ++v) WL[v] = ql[v * st];
+                xch(WL);
+                xch(qme);
                 bad |= hllc<NDIM, 0>(WL, qme, Fv, K);
+                xch(Fv);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sFx[v][epos][wx] = Fv[v];
-                if (x0 + wx == B.nx) reg_put(1, y0 + epos, (NDIM == 3) ? k : 0, Fv);
-            } else if (etype == 3) {
-                double WL[5], Fv[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) WL[v] = sQy[v][wy][epos];
-                bad |= hllc<NDIM, 1>(WL, qme, Fv, K);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) sFy[v][wy][epos] = Fv[v];
-                if (y0 + wy == B.ny) reg_put(3, x0 + epos, (NDIM == 3) ? k : 0, Fv);
+                for (int v = 0; v < NV; ++v) fo[v * st] = Fv[v];
+                if (fy ? (y0 + wy == B.ny) : (x0 + wx == B.nx))
+                    reg_put(fy ? 3 : 1, (fy ? x0 : y0) + epos, (NDIM == 3) ? k : 0, Fv);
             }
             __syncthreads();
 
