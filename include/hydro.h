@@ -223,6 +223,19 @@ const char *hydro_last_error(hydro_ctx_t *ctx);
  * owns.  NULL is ignored. */
 void hydro_destroy(hydro_ctx_t *ctx);
 
+/* Arithmetic check of the device.  The step's results are reproducible bit
+ * for bit on any host only if the device's binary64 division, square root
+ * and fused multiply-add round correctly (to nearest, ties to even, with
+ * subnormals kept), as the step kernels use them.  For i < n this computes,
+ * with the kernels' compiler settings, quot[i] = a[i] / b[i],
+ * root[i] = sqrt(a[i]) and fmad[i] = fma(a[i], b[i], c[i]); all six are
+ * DEVICE pointers of n doubles on the current device, owned by the caller.
+ * Enqueued on `stream` (a hipStream_t; NULL: the default stream) and
+ * asynchronous.  Returns HYDRO_EINVAL for n < 0 or a null pointer with
+ * n > 0, HYDRO_EHIP if the launch fails. */
+int hydro_fp_check(const double *a, const double *b, const double *c, double *quot, double *root,
+                   double *fmad, int64_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,7 @@ TILES = {0: (8, 8), 1: (16, 8), 2: (16, 16)}
 EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create_amr",
            "hydro_set_tuning", "hydro_get_tuning",
            "hydro_fill_guards", "hydro_cfl_dt", "hydro_rk_stage", "hydro_step",
-           "hydro_step_vjp", "hydro_status", "hydro_last_error", "hydro_destroy")
+           "hydro_step_vjp", "hydro_status", "hydro_last_error", "hydro_destroy", "hydro_fp_check")
 FLAG_LEVEL_BY_LEVEL = 1
 
 
@@ -88,6 +88,7 @@ def lib():
             "hydro_status": (C.c_int, [vp, C.POINTER(C.c_int64)]),
             "hydro_last_error": (C.c_char_p, [vp]),
             "hydro_destroy": (None, [vp]),
+            "hydro_fp_check": (C.c_int, [dp, dp, dp, dp, dp, dp, i64, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -136,3 +137,21 @@ def validate(prob) -> int:
     if A is not None:
         return lib().hydro_validate_amr(C.byref(P), B, L, A, nb, int(prob.ncell))
     return lib().hydro_validate(C.byref(P), B, L, nb, int(prob.ncell))
+
+
+def fp_check(a, b, c, stream=None):
+    """Device division, square root and fused multiply-add of float64 CUDA
+    tensors of one shape (hydro_fp_check): returns (a / b, sqrt(a),
+    fma(a, b, c)) computed by the library's kernel."""
+    import torch
+
+    for t in (a, b, c):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.shape != a.shape:
+            raise ValueError("fp_check takes contiguous float64 CUDA tensors of one shape")
+    quot, root, fmad = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib().hydro_fp_check(a.data_ptr(), b.data_ptr(), c.data_ptr(), quot.data_ptr(), root.data_ptr(),
+                              fmad.data_ptr(), a.numel(), C.c_void_p(st.cuda_stream))
+    if rc != HYDRO_OK:
+        raise HydroError(rc, "hydro_fp_check")
+    return quot, root, fmad

@@ -1187,6 +1187,15 @@ const char *hydro_last_error(hydro_ctx_t *c)
     return c->err.c_str();
 }
 
+int hydro_fp_check(const double *a, const double *b, const double *c, double *quot, double *root, double *fmad,
+                   int64_t n, void *stream)
+{
+    if (n < 0) return HYDRO_EINVAL;
+    if (n > 0 && (!a || !b || !c || !quot || !root || !fmad)) return HYDRO_EINVAL;
+    hipError_t e = launch_fp_check(a, b, c, quot, root, fmad, n, (hipStream_t)stream);
+    return e == hipSuccess ? HYDRO_OK : HYDRO_EHIP;
+}
+
 void hydro_destroy(hydro_ctx_t *c)
 {
     if (!c) return;

@@ -95,3 +95,9 @@ def test_validate_amr_meshes_and_broken_tables():
         q = p.copy()
         q.amr[j]["nbr"][2][1] = 1
         assert _hip.validate(q) == _hip.HYDRO_EINVAL
+
+
+def test_fp_check_rejects_bad_arguments_without_a_gpu():
+    L = _hip.lib()
+    assert L.hydro_fp_check(None, None, None, None, None, None, -1, None) == _hip.HYDRO_EINVAL
+    assert L.hydro_fp_check(None, None, None, None, None, None, 4, None) == _hip.HYDRO_EINVAL
