@@ -28,8 +28,6 @@
 // wrap, outflow copy); only the guard layers of faces to another refinement
 // level are read from the array, after k_amr_fill has written them.  A
 // persistent grid walks the work list with a fixed stride.
-#include <algorithm>
-
 #include "hydro_kernels.h"
 
 namespace hydro {
@@ -703,30 +701,6 @@ hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick
     if (nblk <= 0) return hipSuccess;
     if (ndim == 3) k_tele_copy<3><<<nblk, 256, 0, st>>>(a, to_thick ? 1 : 0);
     else k_tele_copy<2><<<nblk, 256, 0, st>>>(a, to_thick ? 1 : 0);
-    return hipGetLastError();
-}
-
-// Element-wise division, square root and fused multiply-add, compiled with
-// the settings of the step kernels (the device-arithmetic check).
-__global__ void __launch_bounds__(256) k_fp_check(const double *__restrict__ a, const double *__restrict__ b,
-                                                  const double *__restrict__ c, double *__restrict__ quot,
-                                                  double *__restrict__ root, double *__restrict__ fmad, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double x = a[i], y = b[i];
-        quot[i] = x / y;
-        root[i] = sqrt(x);
-        fmad[i] = fma(x, y, c[i]);
-    }
-}
-
-hipError_t launch_fp_check(const double *a, const double *b, const double *c, double *quot, double *root,
-                           double *fmad, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    const int64_t want = (n + 255) / 256;
-    const int grid = (int)std::min<int64_t>(want, 65536);
-    k_fp_check<<<grid, 256, 0, st>>>(a, b, c, quot, root, fmad, n);
     return hipGetLastError();
 }
 

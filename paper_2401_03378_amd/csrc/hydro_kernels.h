@@ -107,8 +107,6 @@ hipError_t launch_amr_fill(const AmrArgs &a, int ndim, hipStream_t st);
 hipError_t launch_amr_correct(const AmrArgs &a, int ndim, hipStream_t st);
 hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t st);
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int nitems, hipStream_t st);
-hipError_t launch_fp_check(const double *a, const double *b, const double *c, double *quot, double *root,
-                           double *fmad, int64_t n, hipStream_t st);
 hipError_t launch_vjp_cells(const VjpArgs &a, int ndim, int recon, int grid, hipStream_t st);
 
 }  // namespace hydro
