@@ -19,6 +19,17 @@ def _solver(p, **tune):
     return Solver(p, tuning=tune or None)
 
 
+def _bench_tuning(p):
+    """The autotuner's cached launch configuration for this problem (the one
+    bench.py times), or None."""
+    import json
+    import os
+    from paper_2401_03378_amd import autotune
+    if not os.path.exists(autotune.CACHE):
+        return None
+    return json.load(open(autotune.CACHE)).get(autotune.signature(p), {}).get("tuning")
+
+
 def _rand_cot(p, seed):
     rng = np.random.default_rng(seed)
     return np.where(np.isfinite(p.U0), rng.standard_normal(p.U0.shape), 0.0)
@@ -126,7 +137,7 @@ def test_sedov_step_vjp_full_size_and_rollout():
     dt = O.cfl_dt(p, p.U0)
     g = _rand_cot(p, 8)
     ref = O.step_vjp(p, p.U0, dt, g)
-    S = _solver(p)
+    S = _solver(p, **(_bench_tuning(p) or {}))
     got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
     assert_parity(p, got, ref, "sedov vjp 128^3")
     ost = OracleStepper(p)
