@@ -157,8 +157,38 @@ def compare_forms(indices, log=print):
     return out
 
 
+def compare_telescoping(indices, log=print):
+    """For each named workload, in its tuned launch configuration: hydro_step
+    with the per-stage guard fill against the telescoping step, as JSON lines."""
+    from . import workloads as W
+    from .solver import Solver
+
+    out = []
+    for ci in indices:
+        p = W.config(ci)
+        S = Solver(p)
+        base = tuned_or_search(S, p, log=log)
+        U0 = S.to_device(p.U0)
+        row = {"cfg": ci, "name": p.name, "tuning": base}
+        for label, mode in (("per_stage_fill", 0), ("telescoping", 2)):
+            S.set_tuning(**dict(base, mode=mode))
+            U = U0.clone()
+            for _ in range(2):
+                S.step(U)
+            row[label + "_ms_per_step"] = _time_steps(S, U, 5) * 1e3
+            S.status()
+        print(json.dumps(row), flush=True)
+        out.append(row)
+        S.close()
+    return out
+
+
 if __name__ == "__main__":
     import sys
 
-    compare_forms([int(a) for a in sys.argv[1:]] or [0, 1, 2, 3, 4],
-                  log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    args = sys.argv[1:]
+    quiet = dict(log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    if args and args[0] == "--telescoping":
+        compare_telescoping([int(a) for a in args[1:]] or [0, 1, 2, 3, 4], **quiet)
+    else:
+        compare_forms([int(a) for a in args] or [0, 1, 2, 3, 4], **quiet)
