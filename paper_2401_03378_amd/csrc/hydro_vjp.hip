@@ -590,12 +590,36 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
         const int inc0 = A.inc_start[it.block], inc1 = A.inc_start[it.block + 1];
         for (int k = z0; k < z0 + nzc; ++k) {
             const int64_t ci = cell_at(B, i, j, k);
+            // the cell's own operands first, so their loads overlap the sums below
+            double u[5], go[5], gn[5];
+            load_cons<NDIM>(A.Us, nc, ci, u);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) go[v] = A.gOut[v * nc + ci];
+            if (A.gUn) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) gn[v] = A.gUn[v * nc + ci];
+            }
             double gw[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) gw[v] = 0.0;
-            seg_sum(B, 0, i, xt_at<H>(B, i, j, k), gw);
-            seg_sum(B, 1, j, ci, gw);
-            if constexpr (NDIM == 3) seg_sum(B, 2, k, ci, gw);
+            if (A.nseg == 1) {
+                // one segment per line: every direction's array covers the cell;
+                // all loads issued before the sums (same order of additions)
+                double gd[NDIM][NV];
+                const int64_t xi = xt_at<H>(B, i, j, k);
+#pragma unroll
+                for (int d = 0; d < NDIM; ++d)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) gd[d][v] = A.gW[(int64_t)d * astride + v * nc + (d == 0 ? xi : ci)];
+#pragma unroll
+                for (int d = 0; d < NDIM; ++d)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) gw[v == NDIM + 1 ? 4 : v] += gd[d][v];
+            } else {
+                seg_sum(B, 0, i, xt_at<H>(B, i, j, k), gw);
+                seg_sum(B, 1, j, ci, gw);
+                if constexpr (NDIM == 3) seg_sum(B, 2, k, ci, gw);
+            }
             // guard positions (of this or other blocks) that copy this cell
             for (int e = inc0; e < inc1; ++e) {
                 const int4 q = A.inc[e];                 // x = block, y = dir, z = side, w = kind
@@ -618,18 +642,16 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
                     seg_sum(X, d, gpos, (d == 0) ? xt_at<H>(X, gi, gj, gk) : cell_at(X, gi, gj, gk), gw);
                 }
             }
-            double u[5], gu[5];
-            load_cons<NDIM>(A.Us, nc, ci, u);
+            double gu[5];
             eos_vjp<NDIM>(u, gw, gu, A.g1);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double go = A.gOut[v * nc + ci];
-                const double gs = A.b * go + gu[v];
+                const double gs = A.b * go[v] + gu[v];
                 if (A.last) {
-                    A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + gs;
+                    A.gUn[v * nc + ci] = gn[v] + gs;
                 } else {
                     A.gUs[v * nc + ci] = gs;
-                    if (A.gUn) A.gUn[v * nc + ci] = A.gUn[v * nc + ci] + A.a * go;
+                    if (A.gUn) A.gUn[v * nc + ci] = gn[v] + A.a * go[v];
                 }
             }
         }
