@@ -193,10 +193,9 @@ __device__ __forceinline__ bool recon_cell(const double (&s)[S][5], double (&qm)
     return fb;
 }
 
-// Face state -> conserved U, normal flux F (direction N), 1/rho, sound speed.
+// Face state -> conserved U and normal flux F (direction N).
 template <int NDIM, int N>
-__device__ __forceinline__ void state_flux(const double (&w)[5], double (&u)[5], double (&f)[5], double &r,
-                                           double &c, const Consts &K)
+__device__ __forceinline__ void state_flux(const double (&w)[5], double (&u)[5], double (&f)[5], const Consts &K)
 {
     const double rho = w[0], p = w[4], un = w[1 + N];
     double ke;
@@ -214,8 +213,16 @@ __device__ __forceinline__ void state_flux(const double (&w)[5], double (&u)[5],
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) f[1 + d] = (d == N) ? (fr * un) + p : fr * w[1 + d];
     f[NDIM + 1] = (E + p) * un;
-    r = 1.0 / rho;
-    c = sqrt((K.gamma * p) * r);
+}
+
+// The same, also giving 1/rho and the sound speed.
+template <int NDIM, int N>
+__device__ __forceinline__ void state_flux_rc(const double (&w)[5], double (&u)[5], double (&f)[5], double &r,
+                                              double &c, const Consts &K)
+{
+    state_flux<NDIM, N>(w, u, f, K);
+    r = 1.0 / w[0];
+    c = sqrt((K.gamma * w[4]) * r);
 }
 
 // Flux of the HLLC star region on side K: F*_K = F_K + S_K (U*_K - U_K).
@@ -238,30 +245,59 @@ __device__ __forceinline__ void star_flux(const double (&W)[5], const double (&U
 // HLLC flux at a face normal to N from left/right primitive states, with
 // Davis bounds S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R)
 // and the contact speed S*.  Region: S_L >= 0 -> F_L; S* >= 0 -> F*_L;
-// S_R > 0 -> F*_R; else F_R.  Returns true if either state is non-physical.
-template <int NDIM, int N>
+// S_R > 0 -> F*_R; else F_R.  Every region needs the conserved state and
+// flux of one side only (K = L for the first two, R for the others).  With
+// ONE_SIDE a lane builds those of its side after the wave speeds and the star
+// regions of both sides share one evaluation (fewer instructions and no
+// divergent second star flux); otherwise both sides are built and the region
+// picks one, which the compiler schedules better in the WENO5 kernels.  Both
+// give the same bits.  Returns true if either state is non-physical.
+template <int NDIM, int N, bool ONE_SIDE = false>
 __device__ __forceinline__ bool hllc(const double (&WL)[5], const double (&WR)[5], double (&F)[5], const Consts &K)
 {
     constexpr int NV = NDIM + 2;
     const bool bad = !(WL[0] > 0.0 && WL[4] > 0.0) || !(WR[0] > 0.0 && WR[4] > 0.0);
-    double UL[5], UR[5], FL[5], FR[5], rL, rR, cL, cR;
-    state_flux<NDIM, N>(WL, UL, FL, rL, cL, K);
-    state_flux<NDIM, N>(WR, UR, FR, rR, cR, K);
     const double uL = WL[1 + N], uR = WR[1 + N];
-    const double SL = dmin(uL - cL, uR - cR);
-    const double SR = dmax(uL + cL, uR + cR);
-    const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
-    const double Ss = ((WR[4] - WL[4]) + (mL * uL - mR * uR)) / (mL - mR);
-    if (SL >= 0.0) {
+    if constexpr (ONE_SIDE) {
+        const double rL = 1.0 / WL[0], rR = 1.0 / WR[0];
+        const double cL = sqrt((K.gamma * WL[4]) * rL), cR = sqrt((K.gamma * WR[4]) * rR);
+        const double SL = dmin(uL - cL, uR - cR);
+        const double SR = dmax(uL + cL, uR + cR);
+        const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
+        const double Ss = ((WR[4] - WL[4]) + (mL * uL - mR * uR)) / (mL - mR);
+        const bool subL = !(SL >= 0.0);
+        const bool right = subL && !(Ss >= 0.0);          // F*_R or F_R
+        const bool star = subL && ((Ss >= 0.0) || (SR > 0.0));
+        double W[5];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] = FL[v];
-    } else if (Ss >= 0.0) {
-        star_flux<NDIM, N>(WL, UL, FL, SL, mL, rL, Ss, F);
-    } else if (SR > 0.0) {
-        star_flux<NDIM, N>(WR, UR, FR, SR, mR, rR, Ss, F);
+        for (int v = 0; v < 5; ++v) W[v] = right ? WR[v] : WL[v];
+        double UK[5], FK[5];
+        state_flux<NDIM, N>(W, UK, FK, K);
+        if (star) {
+            star_flux<NDIM, N>(W, UK, FK, right ? SR : SL, right ? mR : mL, right ? rR : rL, Ss, F);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] = FK[v];
+        }
     } else {
+        double UL[5], UR[5], FL[5], FR[5], rL, rR, cL, cR;
+        state_flux_rc<NDIM, N>(WL, UL, FL, rL, cL, K);
+        state_flux_rc<NDIM, N>(WR, UR, FR, rR, cR, K);
+        const double SL = dmin(uL - cL, uR - cR);
+        const double SR = dmax(uL + cL, uR + cR);
+        const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
+        const double Ss = ((WR[4] - WL[4]) + (mL * uL - mR * uR)) / (mL - mR);
+        if (SL >= 0.0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] = FR[v];
+            for (int v = 0; v < NV; ++v) F[v] = FL[v];
+        } else if (Ss >= 0.0) {
+            star_flux<NDIM, N>(WL, UL, FL, SL, mL, rL, Ss, F);
+        } else if (SR > 0.0) {
+            star_flux<NDIM, N>(WR, UR, FR, SR, mR, rR, Ss, F);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] = FR[v];
+        }
     }
     return bad;
 }

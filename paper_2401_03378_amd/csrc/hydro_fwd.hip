@@ -145,7 +145,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 double qa[5], qb[5], qm[5];
                 recon_cell<NDIM, RECON>(s0, qa, qpz);      // cell z0-1: keep its right face
                 recon_cell<NDIM, RECON>(s1, qm, qb);       // cell z0
-                bad |= hllc<NDIM, 2>(qpz, qm, Flo, K);
+                bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Flo, K);
                 if (z0 == 0) reg_put(4, i, j, Flo);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) qpz[v] = qb[v];
@@ -189,7 +189,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                     for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = zw[R - 1][v];
                     double qm[5], qp[5], Fhi[5];
                     recon_cell<NDIM, RECON>(zw, qm, qp);   // cell k+1
-                    bad |= hllc<NDIM, 2>(qpz, qm, Fhi, K);
+                    bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Fhi, K);
                     if (k == B.nz - 1) reg_put(5, i, j, Fhi);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) { Dz[v] = Fhi[v] - Flo[v]; Flo[v] = Fhi[v]; }
@@ -322,13 +322,13 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 double WL[5], Fv[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) WL[v] = sQx[v][ty][tx];
-                bad |= hllc<NDIM, 0>(WL, qmx, Fv, K);
+                bad |= hllc<NDIM, 0, RECON == kPLM>(WL, qmx, Fv, K);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) sFx[v][ty][tx] = Fv[v];
                 if (i == 0) reg_put(0, j, (NDIM == 3) ? k : 0, Fv);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) WL[v] = sQy[v][ty][tx];
-                bad |= hllc<NDIM, 1>(WL, qmy, Fv, K);
+                bad |= hllc<NDIM, 1, RECON == kPLM>(WL, qmy, Fv, K);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) sFy[v][ty][tx] = Fv[v];
                 if (j == 0) reg_put(2, i, (NDIM == 3) ? k : 0, Fv);
@@ -353,7 +353,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 for (int v = 0; v < 5; ++v) WL[v] = ql[v * st];
                 xch(WL);
                 xch(qme);
-                bad |= hllc<NDIM, 0>(WL, qme, Fv, K);
+                bad |= hllc<NDIM, 0, RECON == kPLM>(WL, qme, Fv, K);
                 xch(Fv);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) fo[v * st] = Fv[v];
