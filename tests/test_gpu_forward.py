@@ -71,6 +71,12 @@ SMALL = [
     (3, 1, 3, 12, 3, "outflow", (2, 2, 2)),
     (3, 1, 3, 16, 3, "periodic", (1, 2, 2)),
     (3, 1, 2, 7, 4, "periodic", (2, 2, 1)),
+    # blocks exactly as wide as their guard layers: every guard layer reaches
+    # across the whole neighbour interior
+    (3, 1, 3, 3, 3, "periodic", (2, 2, 2)),
+    (3, 1, 3, 3, 3, "outflow", (2, 1, 2)),
+    (3, 0, 2, 2, 2, "outflow", (2, 2, 2)),
+    (2, 1, 3, 3, 3, "periodic", (3, 2, 1)),
 ]
 
 
