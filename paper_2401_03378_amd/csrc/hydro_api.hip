@@ -428,6 +428,15 @@ AmrArgs amr_args(hydro_ctx *c, double *U)
     g.faces = c->d_faces;
     g.nc = c->ncell;
     g.ng = (c->nblocks > 0) ? c->hb[0].ng : 1;
+    if (c->nblocks > 0) {
+        // every block of a mesh with levels has the same extents
+        const hydro_block_t &B = c->hb[0];
+        const int face = (c->prm.ndim == 3) ? std::max(B.ny * B.nz, std::max(B.nx * B.nz, B.nx * B.ny))
+                                            : std::max(B.nx, B.ny);
+        g.fchunks = (face * g.ng + 255) / 256;
+    } else {
+        g.fchunks = 1;
+    }
     g.nface = c->nface;
     g.idx = 1.0 / c->prm.dx;
     g.idy = 1.0 / c->prm.dy;

@@ -481,18 +481,24 @@ __global__ void __launch_bounds__(256) k_amr_fill(AmrArgs A)
 {
     constexpr int NV = NDIM + 2;
     const int64_t nc = A.nc;
-    // one workgroup per (face of the list, guard layer l = 1 .. ng)
-    for (int w = blockIdx.x; w < A.nlist * A.ng; w += gridDim.x) {
-        const int b = A.list[w / A.ng].x, f = A.list[w / A.ng].y;
-        const int l = 1 + w % A.ng;
+    // fchunks workgroups per face of the list; the face's items (guard layer
+    // l = 1 .. ng, cell of the face) are numbered with the layer fastest, so
+    // the layers of one row (adjacent doubles behind an x face) fall to
+    // neighbouring lanes, and each workgroup takes one 256-item chunk
+    for (int w = blockIdx.x; w < A.nlist * A.fchunks; w += gridDim.x) {
+        const int b = A.list[w / A.fchunks].x, f = A.list[w / A.fchunks].y;
+        const int t0 = (w % A.fchunks) * (int)blockDim.x;
         const int d = f >> 1, side = f & 1;
         const int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
         const DevBlock B = A.blocks[b];
         const DevAmr &M = A.amr[b];
         const int ext[3] = {B.nx, B.ny, B.nz};
         const int n = ext[d], n1 = ext[o1], n2 = (NDIM == 3) ? ext[o2] : 1;
-        for (int t = threadIdx.x; t < n1 * n2; t += blockDim.x) {
-            const int e1 = t % n1, e2 = t / n1;
+        {
+            const int t = t0 + (int)threadIdx.x;
+            if (t >= n1 * n2 * A.ng) continue;
+            const int l = 1 + t % A.ng, e = t / A.ng;
+            const int e1 = e % n1, e2 = e / n1;
             int g[3] = {0, 0, 0};
             g[d] = (side == 0) ? -l : n - 1 + l;
             g[o1] = e1;
@@ -782,8 +788,8 @@ hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_
 hipError_t launch_amr_fill(const AmrArgs &a, int ndim, hipStream_t st)
 {
     if (a.nlist <= 0) return hipSuccess;
-    if (ndim == 3) k_amr_fill<3><<<a.nlist * a.ng, 256, 0, st>>>(a);
-    else k_amr_fill<2><<<a.nlist * a.ng, 256, 0, st>>>(a);
+    if (ndim == 3) k_amr_fill<3><<<a.nlist * a.fchunks, 256, 0, st>>>(a);
+    else k_amr_fill<2><<<a.nlist * a.fchunks, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct AmrArgs {
     const int2 *list;           // fill: (block, face); correction: (block, -)
     int32_t nlist;
     int32_t ng;                 // guard layers (shared by all blocks of a mesh with levels)
+    int32_t fchunks;            // guard fill: workgroups per face (chunks of its layer x cell items)
     int64_t nc;
     int32_t nface;
     double idx, idy, idz;
