@@ -9,7 +9,9 @@ CFL dt reduction plus three fused stage launches (captured in a hipGraph).
 Prints ONE JSON line: zone-updates per second per RK stage, the roofline of
 the dominant kernel (the fused stage kernel, timed with HIP events on its
 own stream), and the CPU oracle timed on a bounded sample of the same
-workload on the host cores.
+workload on the host cores.  The timed loop steps one state, each step
+taking its CFL dt from the maxima the previous step's final stage recorded
+(the same dt bit for bit; --cfl-pass: a separate pass over U).
 """
 import argparse
 import hashlib
@@ -159,6 +161,9 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=10, help="steps timed per stage launch with events")
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 512 MiB device copy")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cfl-pass", action="store_true",
+                    help="compute every step's dt with a separate pass over U (default: from the maxima "
+                         "the previous step's final stage recorded)")
     ap.add_argument("--amr-only", action="store_true",
                     help="only time the two-level AMR workload (prints its JSON object)")
     ap.add_argument("--no-extras", action="store_true",
@@ -193,12 +198,16 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    # a time-stepping loop on one state: each step takes its CFL dt from the
+    # maxima the previous step's final stage recorded (bitwise the same dt as
+    # a separate pass over U; --cfl-pass times that pass instead)
+    fused = not args.cfl_pass
     for _ in range(args.warmup):
-        S.step(U)
+        S.step(U, dt_from_previous=fused)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        S.step(U)
+        S.step(U, dt_from_previous=fused)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     S.status()
@@ -271,7 +280,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sedov3d: 128^3 cells as 512 blocks of 16^3 + 3 guard layers, WENO5 + HLLC "
                                "+ SSP-RK3, CFL 0.5, gamma 1.4, E=1 in r<3.5 cells",
-                   "zones": zones, "rk_stages": prob.rk, "tuning": S.tuning()},
+                   "zones": zones, "rk_stages": prob.rk, "tuning": S.tuning(),
+                   "dt": ("CFL maxima recorded by the previous step's final stage" if fused
+                          else "separate CFL pass over U")},
         "roofline": roof,
         "hbm_effective_frac": round(hbm_frac, 4),
     }

@@ -193,11 +193,21 @@ int hydro_rk_stage(hydro_ctx_t *ctx, int32_t stage, const double *dt_dev,
                    const double *Un, const double *Us, double *Uout);
 
 /* One full step in place on U.  If compute_dt != 0 the CFL dt of U is first
- * written to dt_dev; otherwise the value already in dt_dev is used.  With
- * use_graph, the step is captured into a hipGraph bound to (U, dt_dev,
- * compute_dt) once the same arguments arrive in two consecutive calls, and
- * replayed while they stay the same; other calls launch the kernels
- * directly.  Either way the result is the same bit for bit. */
+ * written to dt_dev; otherwise the value already in dt_dev is used.
+ * compute_dt = HYDRO_DT_FROM_PREVIOUS gives the same dt, bit for bit, for a
+ * caller that steps one state repeatedly: the final stage of such a step
+ * also records the CFL maxima of the state it writes, and the next such
+ * call on the same U takes dt from them instead of reading U again.  The
+ * caller must not write U's interior between the two calls by other means
+ * than this library (the ctx forgets the maxima on hydro_rk_stage,
+ * hydro_set_tuning, any other hydro_step call or a different U, and then
+ * reads U as with 1).  It applies to the persistent mode on meshes without
+ * levels; elsewhere it acts as 1.  With use_graph, the step is captured into
+ * a hipGraph bound to (U, dt_dev, dt mode) once the same arguments arrive in
+ * two consecutive calls, and replayed while they stay the same; other calls
+ * launch the kernels directly.  Either way the result is the same bit for
+ * bit. */
+#define HYDRO_DT_FROM_PREVIOUS 2
 int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
 
 /* Vector-Jacobian product of one step with dt held fixed (the branch

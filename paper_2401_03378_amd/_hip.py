@@ -23,6 +23,7 @@ EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create
            "hydro_fill_guards", "hydro_cfl_dt", "hydro_rk_stage", "hydro_step",
            "hydro_step_vjp", "hydro_status", "hydro_last_error", "hydro_destroy", "hydro_fp_check")
 FLAG_LEVEL_BY_LEVEL = 1
+HYDRO_DT_FROM_PREVIOUS = 2
 
 
 class HydroError(RuntimeError):

@@ -37,6 +37,12 @@ struct hydro_ctx {
     double *d_buf[2] = {nullptr, nullptr};
     double *d_partial = nullptr;
     int partial_cap = 0;
+    // CFL maxima of the state the last fused step wrote (compute_dt 2): the
+    // per-workgroup maxima of its final stage, valid for cfl_next_U until
+    // another call may have changed that state
+    double *d_cflnext = nullptr;
+    int ncflnext = 0;
+    const double *cfl_next_U = nullptr;
     unsigned long long *d_nbad = nullptr;
     hydro_tuning_t tune{};
     std::string err;
@@ -370,8 +376,12 @@ int upload_items(hydro_ctx *c)
         if (c->d_partial) (void)hipFree(c->d_partial);
         c->d_partial = nullptr;
         HIP_TRY(c, hipMalloc(&c->d_partial, sizeof(double) * need));
+        if (c->d_cflnext) (void)hipFree(c->d_cflnext);
+        c->d_cflnext = nullptr;
+        HIP_TRY(c, hipMalloc(&c->d_cflnext, sizeof(double) * need));
         c->partial_cap = need;
     }
+    c->cfl_next_U = nullptr;     // the work list (and grid) may have changed
     return HYDRO_OK;
 }
 
@@ -515,7 +525,7 @@ int enqueue_guards(hydro_ctx *c, double *U, int b0, int nblk, hipStream_t st)
 // One stage in the configured form.  In per-block form Us must be writable
 // (its guards are materialised block by block).
 int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const double *Us, double *Uout,
-                  hipStream_t st)
+                  hipStream_t st, double *cflo = nullptr)
 {
     StageArgs a = stage_args(c, s, dt, Un, Us, Uout);
     if (c->tune.mode == HYDRO_MODE_PERBLOCK) {
@@ -547,6 +557,7 @@ int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const
         if (e != hipSuccess) return hip_fail(c, e, "stage launch");
         return enqueue_amr_correct(c, s, dt, Uout, 0, c->nlev, st);
     }
+    a.cfl_partial = cflo;
     hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, c->tune.variant, true, persistent_grid(c), st);
     if (e != hipSuccess) return hip_fail(c, e, "stage launch");
     return HYDRO_OK;
@@ -556,18 +567,29 @@ int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const
 // writes U in place (it reads U^n only at the cell it writes).
 int enqueue_step_tele(hydro_ctx *c, double *U, double *dt, int compute_dt, hipStream_t st);
 
-int enqueue_step(hydro_ctx *c, double *U, double *dt, int compute_dt, hipStream_t st)
+// dt modes of a step: 0 the caller's dt; 1 the CFL dt of U; 2 the CFL dt
+// from the maxima the previous fused step's final stage recorded for U, and
+// 3 the CFL dt of U; in modes 2 and 3 the final stage records the maxima of
+// the state it writes for the next step.
+int enqueue_step(hydro_ctx *c, double *U, double *dt, int mode, hipStream_t st)
 {
-    if (c->tune.mode == HYDRO_MODE_TELESCOPING) return enqueue_step_tele(c, U, dt, compute_dt, st);
+    if (c->tune.mode == HYDRO_MODE_TELESCOPING) return enqueue_step_tele(c, U, dt, mode, st);
     int rc;
-    if (compute_dt && (rc = enqueue_cfl(c, U, dt, st))) return rc;
+    if (mode == 2) {
+        hipError_t e = launch_cfl_final(c->d_cflnext, c->ncflnext, c->prm.cfl, dt, st);
+        if (e != hipSuccess) return hip_fail(c, e, "cfl launch");
+    } else if (mode && (rc = enqueue_cfl(c, U, dt, st))) {
+        return rc;
+    }
     const int S = c->prm.rk;
     double *in = U;
     for (int s = 1; s <= S; ++s) {
         double *out = (s == S) ? U : c->d_buf[(s - 1) & 1];
-        if ((rc = enqueue_stage(c, s, dt, U, in, out, st))) return rc;
+        double *cflo = (s == S && mode >= 2) ? c->d_cflnext : nullptr;
+        if ((rc = enqueue_stage(c, s, dt, U, in, out, st, cflo))) return rc;
         in = out;
     }
+    if (mode >= 2) c->ncflnext = persistent_grid(c);
     return HYDRO_OK;
 }
 
@@ -1091,6 +1113,7 @@ int hydro_rk_stage(hydro_ctx_t *c, int32_t stage, const double *dt_dev, const do
     if (c->tune.mode == HYDRO_MODE_TELESCOPING)
         return fail(c, HYDRO_EINVAL, "single stages are not defined in the telescoping mode");
     if (Uout == Us) return fail(c, HYDRO_EINVAL, "Uout aliases Us");
+    c->cfl_next_U = nullptr;     // it may write the state a fused step recorded
     return enqueue_stage(c, stage, dt_dev, Un, Us, Uout, c->stream);
 }
 
@@ -1098,9 +1121,17 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
 {
     if (!c || !U || !dt_dev) return fail(c, HYDRO_EINVAL, "null pointer");
     if (c->nitems == 0) return HYDRO_OK;
-    if (!c->tune.use_graph || c->tune.mode == HYDRO_MODE_PERBLOCK)
-        return enqueue_step(c, U, dt_dev, compute_dt, c->stream);
-    const int cdt = compute_dt ? 1 : 0;
+    // dt mode (see enqueue_step): fused only in the persistent form on a mesh
+    // without levels, where the final stage covers every cell in one launch
+    int cdt = compute_dt ? 1 : 0;
+    if (compute_dt == HYDRO_DT_FROM_PREVIOUS && c->tune.mode == HYDRO_MODE_PERSISTENT && !c->amr)
+        cdt = (c->cfl_next_U == U) ? 2 : 3;
+    c->cfl_next_U = (cdt >= 2) ? U : nullptr;
+    if (!c->tune.use_graph || c->tune.mode == HYDRO_MODE_PERBLOCK) {
+        const int rc = enqueue_step(c, U, dt_dev, cdt, c->stream);
+        if (rc) c->cfl_next_U = nullptr;
+        return rc;
+    }
     // The graph is bound to (U, dt, compute_dt).  A call with other arguments
     // is launched directly; it is captured only when the same arguments come
     // twice in a row, so callers that step ever-new buffers (a recomputation
@@ -1110,11 +1141,16 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
     c->l_dt = dt_dev;
     c->l_cdt = cdt;
     const bool bound = c->gexec && c->g_U == U && c->g_dt == dt_dev && c->g_cdt == cdt;
-    if (!bound && !repeat) return enqueue_step(c, U, dt_dev, cdt, c->stream);
+    if (!bound && !repeat) {
+        const int rc = enqueue_step(c, U, dt_dev, cdt, c->stream);
+        if (rc) c->cfl_next_U = nullptr;
+        return rc;
+    }
     if (!bound) {
         drop_graph(c);
         HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
         int rc = enqueue_step(c, U, dt_dev, cdt, c->cap);
+        if (rc) c->cfl_next_U = nullptr;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap, &g);
         if (rc) {
@@ -1242,6 +1278,7 @@ void hydro_destroy(hydro_ctx_t *c)
     (void)hipFree(c->d_buf[0]);
     (void)hipFree(c->d_buf[1]);
     (void)hipFree(c->d_partial);
+    (void)hipFree(c->d_cflnext);
     (void)hipFree(c->d_nbad);
     (void)hipFree(c->d_vjp);
     (void)hipFree(c->d_lines);

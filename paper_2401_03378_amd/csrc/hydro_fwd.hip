@@ -6,6 +6,9 @@
 //               calcLims -> calcFlux -> updSoln -> calcEos, Sec. 4.2).
 //  k_cfl_*      CFL time step: per-workgroup max of the wave-speed sum,
 //               then a one-workgroup reduction to dt on the device.
+//  k_stage_cfl  the stage kernel that also records those maxima for the
+//               state it writes (the last stage of a step whose successor
+//               takes its dt from them).
 //  k_fill_guards  materialised guard fill (the listing's fill_guardcells)
 //               for callers that want guards in the array, and for the
 //               plain per-block launch form.
@@ -41,7 +44,7 @@ __device__ __forceinline__ void set_prio(int p)
     else __builtin_amdgcn_s_setprio(0);
 }
 
-template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF, bool LV = false>
+template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF, bool LV = false, bool CFLO = false>
 __device__ __forceinline__ void stage_body(const StageArgs &A)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
@@ -62,6 +65,9 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
     const Consts K{A.gamma, A.g1, A.ig1};
     const double dt = *A.dt;
     bool bad = false;
+    // CFLO: each thread's maximum of the CFL wave-speed sum of the cells it writes
+    __shared__ double sCfl[CFLO ? NT : 1];
+    if constexpr (CFLO) sCfl[tid] = 0.0;
 
     for (int w = blockIdx.x; w < A.nitems; w += gridDim.x) {
         const WorkItem it = A.items[w];
@@ -379,8 +385,36 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                     else
                         out = fma(A.b, T, A.a * cun[v]);
                     A.Uout[v * nc + ci] = out;
+                    if constexpr (CFLO) cus[v] = out;
+                }
+                if constexpr (CFLO) {
+                    // the CFL wave-speed sum of the new state, as the dt reduction
+                    // would take it from the array at the next step
+                    double wv[5];
+                    bad |= eos<NDIM>(cus, wv, K.g1);
+                    const double r = 1.0 / cus[0];
+                    const double c = sqrt((A.gamma * wv[4]) * r);
+                    double sig = ((fabs(wv[1]) + c) * idxb) + ((fabs(wv[2]) + c) * idyb);
+                    if constexpr (NDIM == 3) sig = sig + ((fabs(wv[3]) + c) * idzb);
+                    const double m = sCfl[tid];
+                    sCfl[tid] = (sig > m) ? sig : m;
                 }
             }
+        }
+    }
+    if constexpr (CFLO) {
+        __syncthreads();
+        double m = sCfl[tid];
+        for (int sh = 32; sh > 0; sh >>= 1) {
+            const double o = __shfl_xor(m, sh, 64);
+            m = (o > m) ? o : m;
+        }
+        __syncthreads();
+        if ((tid & 63) == 0) sCfl[tid >> 6] = m;
+        __syncthreads();
+        if (tid == 0) {
+            for (int q = 1; q < NT / 64; ++q) m = (sCfl[q] > m) ? sCfl[q] : m;
+            A.cfl_partial[blockIdx.x] = m;
         }
     }
     if (bad) atomicAdd(A.nbad, 1ull);
@@ -399,6 +433,14 @@ template <int NDIM, int RECON, int TX, int TY, bool GATHER>
 __global__ void __launch_bounds__(TX *TY) k_stage_pf(StageArgs A)
 {
     stage_body<NDIM, RECON, TX, TY, GATHER, true>(A);
+}
+
+// The plain schedule that also reduces the CFL wave-speed sum of the state it
+// writes (the last stage of a step whose successor takes dt from it).
+template <int NDIM, int RECON, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))) k_stage_cfl(StageArgs A)
+{
+    stage_body<NDIM, RECON, TX, TY, true, false, false, true>(A);
 }
 
 // Meshes with refinement levels: the plain schedule that also writes the
@@ -720,6 +762,10 @@ static hipError_t launch_stage_t(const StageArgs &a, int variant, int grid, hipS
             k_stage_lv<NDIM, RECON, TX, TY><<<grid, TX * TY, 0, st>>>(a);
             return hipGetLastError();
         }
+        if (a.cfl_partial != nullptr) {
+            k_stage_cfl<NDIM, RECON, TX, TY><<<grid, TX * TY, 0, st>>>(a);
+            return hipGetLastError();
+        }
     }
     if (variant == 1)
         k_stage_pf<NDIM, RECON, TX, TY, GATHER><<<grid, TX * TY, 0, st>>>(a);
@@ -764,6 +810,12 @@ static hipError_t launch_cfl_n(const CflArgs &a, int tile, int grid, hipStream_t
     case 1: k_cfl_partial<NDIM, 16, 8><<<grid, 128, 0, st>>>(a); break;
     default: k_cfl_partial<NDIM, 16, 16><<<grid, 256, 0, st>>>(a); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_final(const double *partial, int n, double cfl, double *dt, hipStream_t st)
+{
+    k_cfl_final<<<1, 256, 0, st>>>(partial, n, cfl, dt);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ struct StageArgs {
     unsigned long long *nbad;
     double *freg;               // flux registers (faces with FaceSrc::reg >= 0)
     int32_t nface;              // cells per register slot and variable
+    double *cfl_partial;        // non-null: per-workgroup maxima of the CFL wave-speed sum of Uout
 };
 
 // Coarse-fine faces: guard fill across levels and the flux correction.
@@ -101,6 +102,7 @@ struct VjpArgs {
 hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, int variant, bool gather, int grid,
                         hipStream_t st);
 hipError_t launch_cfl(const CflArgs &a, int ndim, int tile, int grid, double cfl, double *dt, hipStream_t st);
+hipError_t launch_cfl_final(const double *partial, int n, double cfl, double *dt, hipStream_t st);
 hipError_t launch_fill_guards(const GuardArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_fill(const TeleArgs &a, int ndim, int nblk, hipStream_t st);
 hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick, hipStream_t st);

@@ -93,11 +93,15 @@ class Solver:
         dt = self.dt if dt is None else dt
         self._check(self._L.hydro_rk_stage(self.ctx, int(stage), _ptr(dt), _ptr(Un), _ptr(Us), _ptr(Uout)))
 
-    def step(self, U, dt=None):
+    def step(self, U, dt=None, dt_from_previous=False):
         """One step in place.  dt None: CFL dt (left in self.dt); a float or a
-        device tensor: that dt."""
+        device tensor: that dt.  dt_from_previous (with dt None): the same dt,
+        taken from the maxima the previous such step recorded for U when U is
+        the state it wrote and nothing else has written it since
+        (HYDRO_DT_FROM_PREVIOUS)."""
         if dt is None:
-            self._check(self._L.hydro_step(self.ctx, _ptr(U), _ptr(self.dt), 1))
+            mode = _hip.HYDRO_DT_FROM_PREVIOUS if dt_from_previous else 1
+            self._check(self._L.hydro_step(self.ctx, _ptr(U), _ptr(self.dt), mode))
             return self.dt
         if not torch.is_tensor(dt):
             self.dt.fill_(float(dt))
@@ -105,11 +109,11 @@ class Solver:
         self._check(self._L.hydro_step(self.ctx, _ptr(U), _ptr(dt), 0))
         return dt
 
-    def run(self, U, nsteps, record_dt=True):
+    def run(self, U, nsteps, record_dt=True, dt_from_previous=False):
         """nsteps CFL steps in place; returns the dts (device tensor)."""
         dts = torch.empty(nsteps, dtype=torch.float64, device=self.device)
         for n in range(nsteps):
-            self.step(U)
+            self.step(U, dt_from_previous=dt_from_previous)
             if record_dt:
                 dts[n:n + 1].copy_(self.dt)
         return dts

@@ -297,3 +297,35 @@ def test_nonphysical_state_is_reported():
     assert e.value.code == HYDRO_ENONPHYS
     S.status()          # the count was reset
     S.close()
+
+
+@pytest.mark.parametrize("case", ["sedov", "turb", "kh", "batched", "outflow_weno"])
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_dt_from_previous_step_is_the_same_step(case, use_graph):
+    """dt from the maxima the previous step's final stage recorded
+    (HYDRO_DT_FROM_PREVIOUS): the same dts and states, bit for bit, as reading
+    U for every dt; after a stage written into U by hydro_rk_stage the
+    recorded maxima are not used."""
+    p = {"sedov": lambda: W.sedov3d(N=32, n=16),
+         "turb": lambda: W.turb3d(N=32, n=16, seed=4),
+         "kh": lambda: W.kh2d(N=64, seed=1),
+         "batched": lambda: W.batched_uneven(nblocks=40, seed=5),
+         "outflow_weno": lambda: W.random_blocks(3, 10, 3, seed=6, recon=1, rk=3, bc="outflow")}[case]()
+    m = W.interior_mask(p.blocks, p.ncell, p.ndim)
+    out = {}
+    for fused in (False, True):
+        S = _solver(p, use_graph=use_graph)
+        U = S.to_device(p.U0)
+        dts = S.run(U, 5, dt_from_previous=fused).cpu().numpy()
+        # a stage of the caller's own into U, then more steps
+        dt = torch.tensor([float(dts[-1]) * 0.5], dtype=torch.float64, device=U.device)
+        tmp = torch.empty_like(U)
+        assert S._L.hydro_rk_stage(S.ctx, 1, dt.data_ptr(), U.data_ptr(), U.data_ptr(), tmp.data_ptr()) == 0
+        U[:, m] = tmp[:, m]
+        dts2 = S.run(U, 3, dt_from_previous=fused).cpu().numpy()
+        S.status()
+        out[fused] = (U.cpu().numpy(), dts, dts2)
+        S.close()
+    (Ua, da, da2), (Ub, db, db2) = out[False], out[True]
+    assert np.array_equal(da, db) and np.array_equal(da2, db2)
+    assert np.array_equal(Ua[:, m], Ub[:, m])
