@@ -1117,22 +1117,16 @@ int hydro_rk_stage(hydro_ctx_t *c, int32_t stage, const double *dt_dev, const do
     return enqueue_stage(c, stage, dt_dev, Un, Us, Uout, c->stream);
 }
 
-int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
+}  // extern "C"
+
+namespace {
+
+// Enqueue one step with dt mode cdt (see enqueue_step), directly or through
+// the ctx's graph.
+int step_launch(hydro_ctx *c, double *U, double *dt_dev, int cdt)
 {
-    if (!c || !U || !dt_dev) return fail(c, HYDRO_EINVAL, "null pointer");
-    if (c->nitems == 0) return HYDRO_OK;
-    // dt mode (see enqueue_step): fused only in the persistent form on a mesh
-    // without levels, where the final stage covers every cell in one launch
-    int cdt = compute_dt ? 1 : 0;
-    if (compute_dt == HYDRO_DT_FROM_PREVIOUS && c->tune.mode == HYDRO_MODE_PERSISTENT && !c->amr)
-        cdt = (c->cfl_next_U == U) ? 2 : 3;
-    c->cfl_next_U = (cdt >= 2) ? U : nullptr;
-    if (!c->tune.use_graph || c->tune.mode == HYDRO_MODE_PERBLOCK) {
-        const int rc = enqueue_step(c, U, dt_dev, cdt, c->stream);
-        if (rc) c->cfl_next_U = nullptr;
-        return rc;
-    }
-    // The graph is bound to (U, dt, compute_dt).  A call with other arguments
+    if (!c->tune.use_graph || c->tune.mode == HYDRO_MODE_PERBLOCK) return enqueue_step(c, U, dt_dev, cdt, c->stream);
+    // The graph is bound to (U, dt, dt mode).  A call with other arguments
     // is launched directly; it is captured only when the same arguments come
     // twice in a row, so callers that step ever-new buffers (a recomputation
     // from checkpoints) pay no capture per step.
@@ -1141,16 +1135,11 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
     c->l_dt = dt_dev;
     c->l_cdt = cdt;
     const bool bound = c->gexec && c->g_U == U && c->g_dt == dt_dev && c->g_cdt == cdt;
-    if (!bound && !repeat) {
-        const int rc = enqueue_step(c, U, dt_dev, cdt, c->stream);
-        if (rc) c->cfl_next_U = nullptr;
-        return rc;
-    }
+    if (!bound && !repeat) return enqueue_step(c, U, dt_dev, cdt, c->stream);
     if (!bound) {
         drop_graph(c);
         HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
         int rc = enqueue_step(c, U, dt_dev, cdt, c->cap);
-        if (rc) c->cfl_next_U = nullptr;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap, &g);
         if (rc) {
@@ -1170,6 +1159,26 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
     }
     HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
     return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
+{
+    if (!c || !U || !dt_dev) return fail(c, HYDRO_EINVAL, "null pointer");
+    if (c->nitems == 0) return HYDRO_OK;
+    // dt mode (see enqueue_step): fused only in the persistent form on a mesh
+    // without levels, where the final stage covers every cell in one launch
+    int cdt = compute_dt ? 1 : 0;
+    if (compute_dt == HYDRO_DT_FROM_PREVIOUS && c->tune.mode == HYDRO_MODE_PERSISTENT && !c->amr)
+        cdt = (c->cfl_next_U == U) ? 2 : 3;
+    // the recorded maxima describe U only once this step is enqueued
+    c->cfl_next_U = nullptr;
+    const int rc = step_launch(c, U, dt_dev, cdt);
+    if (rc == HYDRO_OK && cdt >= 2) c->cfl_next_U = U;
+    return rc;
 }
 
 int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const double *gUnext, double *gUn)
