@@ -329,3 +329,39 @@ def test_dt_from_previous_step_is_the_same_step(case, use_graph):
     (Ua, da, da2), (Ub, db, db2) = out[False], out[True]
     assert np.array_equal(da, db) and np.array_equal(da2, db2)
     assert np.array_equal(Ua[:, m], Ub[:, m])
+
+
+def test_dt_from_previous_with_two_states_and_levels():
+    """Alternating two states, each call finds maxima recorded for the other
+    state and reads U; on a mesh with levels the mode reads U every step.
+    Both give the dts and states of the plain CFL step bit for bit."""
+    p = W.sedov3d(N=32, n=16)
+    m = W.interior_mask(p.blocks, p.ncell, p.ndim)
+    res = {}
+    for fused in (False, True):
+        S = _solver(p)
+        A, B = S.to_device(p.U0), S.to_device(p.U0)
+        B[:, m] = B[:, m] * 1.01
+        dts = []
+        for n in range(4):
+            for X in (A, B):
+                S.step(X, dt_from_previous=fused)
+                dts.append(float(S.dt.item()))
+        S.status()
+        res[fused] = (A.cpu().numpy(), B.cpu().numpy(), dts)
+        S.close()
+    assert res[False][2] == res[True][2]
+    assert np.array_equal(res[False][0][:, m], res[True][0][:, m])
+    assert np.array_equal(res[False][1][:, m], res[True][1][:, m])
+    from paper_2401_03378_amd.solver import Solver
+    a = W.amr_problem(3, NBc=(2, 2, 2), n=8, ng=3, recon=W.WENO5, rk=3, flow="blob", refine=[(0, 0, 0)])
+    ma = W.interior_mask(a.blocks, a.ncell, 3)
+    out = []
+    for fused in (False, True):
+        S = Solver(a)
+        V = S.to_device(a.U0)
+        d = S.run(V, 3, dt_from_previous=fused).cpu().numpy()
+        S.status()
+        out.append((V.cpu().numpy(), d))
+        S.close()
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][0][:, ma], out[1][0][:, ma])
