@@ -27,8 +27,11 @@ def field_errors(prob, Ug, Uo):
     return out
 
 
-def assert_parity(prob, Ug, Uo, what=""):
+def assert_parity(prob, Ug, Uo, what="", bitwise=False):
+    """The tolerance above; with bitwise, also no cell may differ in any bit
+    (the forward step: same arithmetic in the same order on both sides)."""
     errs = field_errors(prob, Ug, Uo)
     for v, (rel, nbits) in enumerate(errs):
         assert rel <= RTOL, f"{what} field {v}: rel err {rel:.3e} ({nbits} cells differ)"
+        assert not bitwise or nbits == 0, f"{what} field {v}: {nbits} cells differ in some bit (rel err {rel:.3e})"
     return errs

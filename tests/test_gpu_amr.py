@@ -40,7 +40,7 @@ def test_amr_parity(ndim, recon, rk, n, ng, NBc, lbl):
         Ug = U.cpu().numpy()
         S.close()
         np.testing.assert_array_equal(dtg, np.array(dto))
-        assert_parity(p, Ug, Uo, f"amr {ndim}d recon {recon} tile {tile} lbl {lbl}")
+        assert_parity(p, Ug, Uo, f"amr {ndim}d recon {recon} tile {tile} lbl {lbl}", bitwise=True)
         m = W.interior_mask(p.blocks, p.ncell, ndim)
         assert np.array_equal(Ug[:, m], Uo[:, m])
 

@@ -92,7 +92,7 @@ def test_parity_small_all_tiles(ndim, recon, rk, n, ng, bc, NB):
     for tile, zchunk, variant in combos:
         Ug, dtg = _gpu_run(p, 3, tile=tile, zchunk=zchunk, variant=variant)
         assert np.array_equal(dtg, dto), (tile, zchunk, dtg, dto)
-        assert_parity(p, Ug, Uo, f"tile {tile} zchunk {zchunk} variant {variant}")
+        assert_parity(p, Ug, Uo, f"tile {tile} zchunk {zchunk} variant {variant}", bitwise=True)
         if first is None:
             first = Ug
         else:
@@ -105,7 +105,7 @@ def test_sod_full_config():
     Uo, dto = _ora_run(p, p.nsteps)
     Ug, dtg = _gpu_runs(p, p.nsteps)
     assert np.array_equal(dtg, dto)
-    errs = assert_parity(p, Ug, Uo, "sod2d")
+    errs = assert_parity(p, Ug, Uo, "sod2d", bitwise=True)
     print("sod2d field errors", errs)
 
 
@@ -114,7 +114,7 @@ def test_sedov_full_config():
     Uo, dto = _ora_run(p, p.nsteps)
     Ug, dtg = _gpu_runs(p, p.nsteps)
     np.testing.assert_array_equal(dtg, dto)
-    errs = assert_parity(p, Ug, Uo, "sedov3d")
+    errs = assert_parity(p, Ug, Uo, "sedov3d", bitwise=True)
     print("sedov3d field errors", errs)
 
 
@@ -123,7 +123,7 @@ def test_batched_full_size_two_steps():
     Uo, dto = _ora_run(p, 2)
     Ug, dtg = _gpu_runs(p, 2)
     np.testing.assert_array_equal(dtg, dto)
-    assert_parity(p, Ug, Uo, "batched")
+    assert_parity(p, Ug, Uo, "batched", bitwise=True)
 
 
 def test_batched_subset_all_steps():
@@ -131,7 +131,7 @@ def test_batched_subset_all_steps():
     Uo, dto = _ora_run(p, 10)
     Ug, dtg = _gpu_run(p, 10)
     np.testing.assert_array_equal(dtg, dto)
-    assert_parity(p, Ug, Uo, "batched-256")
+    assert_parity(p, Ug, Uo, "batched-256", bitwise=True)
 
 
 def test_kh_full_config():
@@ -139,7 +139,7 @@ def test_kh_full_config():
     Uo, dto = _ora_run(p, p.nsteps)
     Ug, dtg = _gpu_runs(p, p.nsteps)
     np.testing.assert_array_equal(dtg, dto)
-    assert_parity(p, Ug, Uo, "kh2d")
+    assert_parity(p, Ug, Uo, "kh2d", bitwise=True)
 
 
 def test_turbulence_full_size_one_step():
@@ -147,7 +147,7 @@ def test_turbulence_full_size_one_step():
     Uo, dto = _ora_run(p, 1)
     Ug, dtg = _gpu_runs(p, 1)
     np.testing.assert_array_equal(dtg, dto)
-    assert_parity(p, Ug, Uo, "turb3d")
+    assert_parity(p, Ug, Uo, "turb3d", bitwise=True)
 
 
 def test_turbulence_small_all_steps():
@@ -155,7 +155,7 @@ def test_turbulence_small_all_steps():
     Uo, dto = _ora_run(p, 5)
     Ug, dtg = _gpu_run(p, 5)
     np.testing.assert_array_equal(dtg, dto)
-    assert_parity(p, Ug, Uo, "turb3d-64")
+    assert_parity(p, Ug, Uo, "turb3d-64", bitwise=True)
 
 
 @pytest.mark.parametrize("mode_kw", [dict(mode=1), dict(use_graph=0), dict(grid=37), dict(grid=256, xcd=1),
@@ -186,7 +186,7 @@ def test_stage_and_dt_entry_points():
     S.rk_stage(3, U, B2, U3)
     ref = p.U0.copy()
     O.step(p, ref, float(dt.item()))
-    assert_parity(p, U3.cpu().numpy(), ref, "stages")
+    assert_parity(p, U3.cpu().numpy(), ref, "stages", bitwise=True)
     Ustep = S.to_device(p.U0)
     S.step(Ustep)
     m = W.interior_mask(p.blocks, p.ncell, 3)
