@@ -206,3 +206,19 @@ def test_step_autograd_function_and_central_differences():
             break
     S.close()
     assert good >= 8
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_random_problems_step_vjp(k):
+    """Step VJPs of seeded random problems (the first eight of the forward
+    tests' random cases) against the oracle's adjoint."""
+    from test_gpu_forward import RANDOM_CASES
+    ndim, recon, rk, n, ng, bc, NB, amp, seed, tune = RANDOM_CASES[k]
+    p = W.random_blocks(ndim, n, ng, seed, recon=recon, rk=rk, bc=bc, NB=NB, amp=amp)
+    dt = O.cfl_dt(p, p.U0)
+    g = _rand_cot(p, seed)
+    ref = O.step_vjp(p, p.U0, dt, g)
+    S = _solver(p, **tune)
+    got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
+    assert_parity(p, got, ref, f"random vjp {k}")
+    S.close()

@@ -365,3 +365,44 @@ def test_dt_from_previous_with_two_states_and_levels():
         out.append((V.cpu().numpy(), d))
         S.close()
     assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][0][:, ma], out[1][0][:, ma])
+
+
+# Seeded random problems (dimension, reconstruction, RK order, block size and
+# grid, guard width, boundary kind, state amplitude) with random launch
+# configurations; drawn once with numpy.random.default_rng(20240106), keeping
+# those the oracle steps without a non-physical state.
+RANDOM_CASES = [
+    (3, 1, 3, 10, 4, 'outflow', (1, 1, 1), 0.3, 527, {'tile': 1, 'zchunk': 3, 'grid': 64, 'xcd': 1, 'variant': 1}),
+    (3, 0, 3, 12, 3, 'outflow', (1, 3, 2), 0.6, 944, {'tile': 2, 'zchunk': 3, 'grid': 64, 'xcd': 1, 'variant': 0}),
+    (2, 1, 2, 6, 3, 'periodic', (3, 2, 1), 0.6, 174, {'tile': 2, 'zchunk': 3, 'grid': 0, 'xcd': 1, 'variant': 1}),
+    (2, 1, 3, 7, 3, 'periodic', (1, 3, 1), 0.3, 909, {'tile': 0, 'zchunk': 3, 'grid': 64, 'xcd': 1, 'variant': 1}),
+    (3, 1, 2, 12, 4, 'outflow', (2, 1, 1), 0.6, 47, {'tile': 2, 'zchunk': 0, 'grid': 0, 'xcd': 2, 'variant': 1}),
+    (2, 0, 3, 18, 2, 'outflow', (2, 2, 1), 0.6, 445, {'tile': 0, 'zchunk': 0, 'grid': 0, 'xcd': 1, 'variant': 0}),
+    (3, 0, 3, 10, 3, 'outflow', (2, 3, 2), 0.6, 183, {'tile': 1, 'zchunk': 5, 'grid': 0, 'xcd': 1, 'variant': 1}),
+    (3, 0, 2, 7, 2, 'outflow', (3, 2, 1), 0.6, 36, {'tile': 1, 'zchunk': 0, 'grid': 0, 'xcd': 0, 'variant': 1}),
+    (3, 0, 3, 5, 3, 'outflow', (3, 1, 2), 0.3, 318, {'tile': 1, 'zchunk': 5, 'grid': 64, 'xcd': 1, 'variant': 0}),
+    (3, 1, 2, 9, 3, 'periodic', (2, 1, 2), 0.3, 848, {'tile': 2, 'zchunk': 0, 'grid': 7, 'xcd': 2, 'variant': 0}),
+    (2, 0, 3, 4, 3, 'outflow', (3, 2, 1), 0.6, 860, {'tile': 0, 'zchunk': 3, 'grid': 0, 'xcd': 0, 'variant': 1}),
+    (3, 1, 3, 10, 3, 'periodic', (3, 2, 2), 0.6, 582, {'tile': 1, 'zchunk': 5, 'grid': 0, 'xcd': 0, 'variant': 1}),
+    (2, 0, 2, 7, 3, 'periodic', (3, 2, 1), 0.3, 194, {'tile': 2, 'zchunk': 0, 'grid': 64, 'xcd': 2, 'variant': 0}),
+    (3, 0, 2, 9, 2, 'outflow', (2, 2, 2), 0.3, 307, {'tile': 1, 'zchunk': 0, 'grid': 0, 'xcd': 2, 'variant': 0}),
+    (2, 0, 3, 15, 2, 'outflow', (3, 2, 1), 0.3, 77, {'tile': 1, 'zchunk': 5, 'grid': 0, 'xcd': 1, 'variant': 1}),
+    (3, 0, 3, 3, 3, 'periodic', (2, 2, 2), 0.6, 836, {'tile': 1, 'zchunk': 0, 'grid': 0, 'xcd': 0, 'variant': 0}),
+    (2, 0, 3, 16, 3, 'outflow', (1, 3, 1), 0.6, 212, {'tile': 1, 'zchunk': 0, 'grid': 0, 'xcd': 2, 'variant': 1}),
+    (2, 0, 3, 7, 3, 'outflow', (2, 2, 1), 0.3, 437, {'tile': 0, 'zchunk': 0, 'grid': 0, 'xcd': 0, 'variant': 0}),
+    (2, 0, 3, 4, 2, 'periodic', (2, 1, 1), 0.3, 668, {'tile': 2, 'zchunk': 5, 'grid': 7, 'xcd': 1, 'variant': 0}),
+    (3, 0, 3, 11, 2, 'periodic', (3, 3, 2), 0.6, 104, {'tile': 1, 'zchunk': 5, 'grid': 7, 'xcd': 1, 'variant': 0}),
+    (2, 0, 3, 9, 3, 'periodic', (3, 2, 1), 0.3, 272, {'tile': 2, 'zchunk': 3, 'grid': 0, 'xcd': 2, 'variant': 1}),
+    (3, 1, 3, 8, 3, 'outflow', (2, 1, 1), 0.6, 530, {'tile': 0, 'zchunk': 0, 'grid': 64, 'xcd': 0, 'variant': 0}),
+    (3, 1, 3, 4, 4, 'periodic', (1, 2, 2), 0.3, 504, {'tile': 0, 'zchunk': 0, 'grid': 0, 'xcd': 2, 'variant': 0}),
+    (3, 0, 3, 5, 3, 'periodic', (3, 3, 2), 0.6, 505, {'tile': 2, 'zchunk': 0, 'grid': 0, 'xcd': 2, 'variant': 1}),
+]
+
+
+@pytest.mark.parametrize("ndim,recon,rk,n,ng,bc,NB,amp,seed,tune", RANDOM_CASES)
+def test_random_problems_bit_for_bit(ndim, recon, rk, n, ng, bc, NB, amp, seed, tune):
+    p = W.random_blocks(ndim, n, ng, seed, recon=recon, rk=rk, bc=bc, NB=NB, amp=amp)
+    Uo, dto = _ora_run(p, 3)
+    Ug, dtg = _gpu_run(p, 3, **tune)
+    assert np.array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, f"random {ndim}d recon {recon} n {n} ng {ng} {bc} {NB} {tune}", bitwise=True)
