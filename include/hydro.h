@@ -221,6 +221,20 @@ int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
 int hydro_step_vjp(hydro_ctx_t *ctx, const double *Un, const double *dt_dev,
                    const double *gUnext, double *gUn);
 
+/* hydro_step_vjp with the stage inputs of the step supplied instead of
+ * recomputed (the stages of the Sec. 4.2 step, reversed one by one).
+ * stages is a host array of S-1 device pointers (S = params.rk):
+ * stages[s-2] holds U_s, the output of hydro_rk_stage stage s-1 for this Un
+ * and dt_dev (interiors are read; guard values are
+ * gathered from their sources, as in the step).  The caller owns the buffers
+ * and keeps them alive until the enqueued work completes.  For a caller that
+ * has just run the step stage by stage (a checkpointed rollout recomputing a
+ * segment) it saves the S-1 stage launches; with those stage inputs the
+ * result is bit for bit that of hydro_step_vjp.  HYDRO_EINVAL if stages or
+ * one of its pointers is null or gUn aliases gUnext or a stage input. */
+int hydro_step_vjp_stages(hydro_ctx_t *ctx, const double *Un, const double *const *stages,
+                          const double *dt_dev, const double *gUnext, double *gUn);
+
 /* Wait for the ctx's stream; *n_nonphys (may be NULL) receives the number of
  * non-physical events counted since the last call, then the count is reset.
  * Returns HYDRO_ENONPHYS if that number is non-zero. */

@@ -21,7 +21,8 @@ TILES = {0: (8, 8), 1: (16, 8), 2: (16, 16)}
 EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create_amr",
            "hydro_set_tuning", "hydro_get_tuning",
            "hydro_fill_guards", "hydro_cfl_dt", "hydro_rk_stage", "hydro_step",
-           "hydro_step_vjp", "hydro_status", "hydro_last_error", "hydro_destroy", "hydro_fp_check")
+           "hydro_step_vjp", "hydro_step_vjp_stages", "hydro_status", "hydro_last_error", "hydro_destroy",
+           "hydro_fp_check")
 FLAG_LEVEL_BY_LEVEL = 1
 HYDRO_DT_FROM_PREVIOUS = 2
 
@@ -86,6 +87,7 @@ def lib():
             "hydro_rk_stage": (C.c_int, [vp, i32, dp, dp, dp, dp]),
             "hydro_step": (C.c_int, [vp, dp, dp, i32]),
             "hydro_step_vjp": (C.c_int, [vp, dp, dp, dp, dp]),
+            "hydro_step_vjp_stages": (C.c_int, [vp, dp, C.POINTER(vp), dp, dp, dp]),
             "hydro_status": (C.c_int, [vp, C.POINTER(C.c_int64)]),
             "hydro_last_error": (C.c_char_p, [vp]),
             "hydro_destroy": (None, [vp]),

@@ -9,9 +9,11 @@ per-step transpose is the library's hydro_step_vjp.
 Checkpointing: the forward rollout stores the state every k steps; the
 backward pass walks the segments in reverse, recomputes a segment's step
 inputs from its checkpoint, then applies the step VJPs in reverse.  Memory is
-(N/k + k) states instead of N.  The rollout logic is written against a small
-stepper interface (step / step_vjp / copy) so that it can be exercised with
-any implementation of a step.
+(N/k + k) states instead of N, plus the stage inputs of the recomputed steps
+(S-1 states each), which their VJPs then need not recompute.  The rollout
+logic is written against a small stepper interface (step / step_vjp / copy,
+optionally step_keep) so that it can be exercised with any implementation of
+a step.
 """
 from __future__ import annotations
 
@@ -26,40 +28,86 @@ class Tape:
         self.k = k
         self.checkpoints = {}   # step index -> state before that step
         self.dts = []
+        self.tail = {}          # step index -> (state before it, kept data), last segment
         self.recomputed_steps = 0
 
 
-def rollout(stepper, U0, nsteps, k, dts=None):
+def rollout(stepper, U0, nsteps, k, dts=None, keep_last=False):
     """Advance a copy of U0 by nsteps; returns (U_N, tape).  dts: optional
-    fixed time steps; otherwise each step takes its CFL dt (recorded)."""
+    fixed time steps; otherwise each step takes its CFL dt (recorded).
+
+    keep_last (for a stepper with step_keep): the steps of the last segment
+    run out of place and the tape keeps their inputs and kept data, which the
+    backward pass would otherwise recompute first and then hold at once
+    anyway; it uses them and releases them.  Without a backward pass this
+    holds k states and their kept data for nothing."""
     if k < 1:
         raise ValueError("checkpoint interval must be >= 1")
     tape = Tape(k)
+    keep = getattr(stepper, "step_keep", None) if keep_last else None
+    last = ((nsteps - 1) // k) * k
     U = stepper.copy(U0)
     for n in range(nsteps):
-        if n % k == 0:
-            tape.checkpoints[n] = stepper.copy(U)
-        dt = stepper.step(U, None if dts is None else dts[n])
+        dtn = None if dts is None else dts[n]
+        if keep is not None and n >= last:
+            # out of place from here on: U itself is the checkpoint
+            if n == last:
+                tape.checkpoints[n] = U
+            Unext, aux, dt = keep(U, dtn)
+            tape.tail[n] = (U, aux)
+            U = Unext
+        else:
+            if n % k == 0:
+                tape.checkpoints[n] = stepper.copy(U)
+            dt = stepper.step(U, dtn)
         tape.dts.append(float(dt))
     return U, tape
 
 
 def rollout_vjp(stepper, tape, gUN):
-    """Cotangent of U0 given the cotangent of U_N, by segments in reverse."""
+    """Cotangent of U0 given the cotangent of U_N, by segments in reverse.
+
+    A stepper with step_keep(Un, dt) -> (U^{n+1}, kept, dt) recomputes a
+    segment's steps out of place and keeps what step_vjp(Un, g, dt, kept)
+    would otherwise recompute (the stage inputs); the last step of a segment
+    is not recomputed forward, so its VJP recomputes its own (except in a
+    last segment kept by the forward pass).  A kept last segment is used once:
+    the tape then falls back to recomputing it."""
     nsteps = len(tape.dts)
+    keep = getattr(stepper, "step_keep", None)
     g = gUN
     starts = sorted(tape.checkpoints)
     for s0 in reversed(starts):
         s1 = min(s0 + tape.k, nsteps)
-        # recompute the inputs of steps s0 .. s1-1
-        states = [stepper.copy(tape.checkpoints[s0])]
-        for n in range(s0, s1 - 1):
-            U = stepper.copy(states[-1])
-            stepper.step(U, tape.dts[n])
-            tape.recomputed_steps += 1
-            states.append(U)
+        if s0 in tape.tail:
+            # the last segment as the forward pass kept it
+            states = [tape.tail[n][0] for n in range(s0, s1)]
+            kept = [tape.tail[n][1] for n in range(s0, s1)]
+            tape.tail = {}
+        else:
+            # recompute the inputs of steps s0 .. s1-1; step_keep leaves its
+            # input as it is, so the checkpoint itself serves
+            ck = tape.checkpoints[s0]
+            states = [ck if keep is not None else stepper.copy(ck)]
+            kept = []
+            for n in range(s0, s1 - 1):
+                if keep is None:
+                    U = stepper.copy(states[-1])
+                    stepper.step(U, tape.dts[n])
+                    kept.append(None)
+                else:
+                    U, aux, _ = keep(states[-1], tape.dts[n])
+                    kept.append(aux)
+                tape.recomputed_steps += 1
+                states.append(U)
+            kept.append(None)
         for n in range(s1 - 1, s0 - 1, -1):
-            g = stepper.step_vjp(states[n - s0], g, tape.dts[n])
+            i = n - s0
+            if kept[i] is None:
+                g = stepper.step_vjp(states[i], g, tape.dts[n])
+            else:
+                g = stepper.step_vjp(states[i], g, tape.dts[n], kept[i])
+            states[i] = kept[i] = None
     return g
 
 
@@ -76,8 +124,14 @@ class TorchStepper:
         d = self.S.step(U, dt)
         return float(d.item()) if torch.is_tensor(d) else float(d)
 
-    def step_vjp(self, Un, g, dt):
-        return self.S.step_vjp(Un, g.contiguous(), dt)
+    def step_keep(self, Un, dt=None):
+        if dt is None:
+            dt = float(self.S.cfl_dt(Un).item())
+        Unext, stages = self.S.step_keep(Un, dt)
+        return Unext, stages, dt
+
+    def step_vjp(self, Un, g, dt, stages=None):
+        return self.S.step_vjp(Un, g.contiguous(), dt, stages=stages)
 
 
 class HydroStep(torch.autograd.Function):
@@ -104,7 +158,7 @@ class HydroRollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U0, solver, nsteps, k):
         st = TorchStepper(solver)
-        UN, tape = rollout(st, U0.detach(), nsteps, k)
+        UN, tape = rollout(st, U0.detach(), nsteps, k, keep_last=True)
         ctx.stepper = st
         ctx.tape = tape
         return UN
@@ -140,7 +194,7 @@ def time_rollouts(cases=((3, 50, 10), (1, 20, 5), (4, 10, 5))):
         st = TorchStepper(S)
         U0 = S.to_device(p.U0)
         # warm-up rollout of the same shape (graph capture, VJP scratch, allocator)
-        UN, tape = rollout(st, U0, nsteps, k)
+        UN, tape = rollout(st, U0, nsteps, k, keep_last=True)
         rollout_vjp(st, tape, torch.nan_to_num(UN).clone())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -148,7 +202,7 @@ def time_rollouts(cases=((3, 50, 10), (1, 20, 5), (4, 10, 5))):
         torch.cuda.synchronize()
         tf = time.perf_counter() - t0
         t0 = time.perf_counter()
-        UN, tape = rollout(st, U0, nsteps, k)
+        UN, tape = rollout(st, U0, nsteps, k, keep_last=True)
         rollout_vjp(st, tape, torch.nan_to_num(UN).clone())
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0

@@ -1181,25 +1181,39 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
     return rc;
 }
 
-int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const double *gUnext, double *gUn)
+// The step VJP; stages (S-1 device pointers) holds the stage inputs U_2 ..
+// U_S, or is null, and then they are recomputed from Un into the ctx's
+// stage buffers.
+static int step_vjp(hydro_ctx_t *c, const double *Un, const double *const *stages, const double *dt_dev,
+                    const double *gUnext, double *gUn)
 {
     if (!c || !Un || !dt_dev || !gUnext || !gUn) return fail(c, HYDRO_EINVAL, "null pointer");
     if (gUn == gUnext) return fail(c, HYDRO_EINVAL, "gUn aliases gUnext");
     if (c->tune.mode == HYDRO_MODE_TELESCOPING)
         return fail(c, HYDRO_EINVAL, "the adjoint is defined for the per-stage-fill step only");
     if (c->amr) return fail(c, HYDRO_EINVAL, "the adjoint is defined on meshes without refinement levels");
+    const int S = c->prm.rk, nd = c->prm.ndim;
+    if (stages)
+        for (int s = 0; s < S - 1; ++s) {
+            if (!stages[s]) return fail(c, HYDRO_EINVAL, "null stage input pointer");
+            if (stages[s] == gUn) return fail(c, HYDRO_EINVAL, "gUn aliases a stage input");
+        }
     if (c->nitems == 0) return HYDRO_OK;
     int rc = setup_vjp(c);
     if (rc) return rc;
     hipStream_t st = c->stream;
-    const int S = c->prm.rk, nd = c->prm.ndim;
     const size_t per = (size_t)c->nv * (size_t)c->ncell;
-    // forward recomputation of the stage inputs U_2 .. U_S
     const double *Us_of[4] = {nullptr, Un, c->d_buf[0], c->d_buf[1]};
-    for (int s = 1; s < S; ++s) {
-        StageArgs a = stage_args(c, s, dt_dev, Un, Us_of[s], c->d_buf[s - 1]);
-        hipError_t e = launch_stage(a, nd, c->prm.recon, c->tune.tile, c->tune.variant, true, persistent_grid(c), st);
-        if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+    if (stages) {
+        for (int s = 2; s <= S; ++s) Us_of[s] = stages[s - 2];
+    } else {
+        // forward recomputation of the stage inputs U_2 .. U_S
+        for (int s = 1; s < S; ++s) {
+            StageArgs a = stage_args(c, s, dt_dev, Un, Us_of[s], c->d_buf[s - 1]);
+            hipError_t e = launch_stage(a, nd, c->prm.recon, c->tune.tile, c->tune.variant, true,
+                                        persistent_grid(c), st);
+            if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+        }
     }
     HIP_TRY(c, hipMemsetAsync(gUn, 0, sizeof(double) * per, st));
     const size_t narr = (size_t)nd * c->nseg;
@@ -1245,6 +1259,18 @@ int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const
         g = gbuf[q];
     }
     return HYDRO_OK;
+}
+
+int hydro_step_vjp(hydro_ctx_t *c, const double *Un, const double *dt_dev, const double *gUnext, double *gUn)
+{
+    return step_vjp(c, Un, nullptr, dt_dev, gUnext, gUn);
+}
+
+int hydro_step_vjp_stages(hydro_ctx_t *c, const double *Un, const double *const *stages, const double *dt_dev,
+                          const double *gUnext, double *gUn)
+{
+    if (!stages) return fail(c, HYDRO_EINVAL, "null pointer");
+    return step_vjp(c, Un, stages, dt_dev, gUnext, gUn);
 }
 
 int hydro_status(hydro_ctx_t *c, int64_t *n_nonphys)

@@ -118,13 +118,42 @@ class Solver:
                 dts[n:n + 1].copy_(self.dt)
         return dts
 
-    def step_vjp(self, Un, gUnext, dt, gUn=None):
-        if not torch.is_tensor(dt):
-            d = torch.full((1,), float(dt), dtype=torch.float64, device=self.device)
-        else:
-            d = dt
+    def _dt_tensor(self, dt):
+        if torch.is_tensor(dt):
+            return dt
+        return torch.full((1,), float(dt), dtype=torch.float64, device=self.device)
+
+    def step_keep(self, Un, dt):
+        """One step at dt out of place, stage by stage (hydro_rk_stage):
+        returns (U^{n+1}, [U_2 .. U_S]), the stage inputs as step_vjp takes
+        them.  Un is not changed."""
+        d = self._dt_tensor(dt)
+        S = int(self.prob.rk)
+        stages = []
+        Us = Un
+        for s in range(1, S):
+            out = torch.empty_like(Un)
+            self.rk_stage(s, Un, Us, out, d)
+            stages.append(out)
+            Us = out
+        Unext = torch.empty_like(Un)
+        self.rk_stage(S, Un, Us, Unext, d)
+        return Unext, stages
+
+    def step_vjp(self, Un, gUnext, dt, gUn=None, stages=None):
+        """gUn = (dU^{n+1}/dU^n)^T gUnext at fixed dt.  stages: the stage
+        inputs [U_2 .. U_S] of this step (from step_keep), used in place of
+        recomputing them."""
+        d = self._dt_tensor(dt)
         gUn = torch.empty_like(Un) if gUn is None else gUn
-        self._check(self._L.hydro_step_vjp(self.ctx, _ptr(Un), _ptr(d), _ptr(gUnext), _ptr(gUn)))
+        if stages is None:
+            self._check(self._L.hydro_step_vjp(self.ctx, _ptr(Un), _ptr(d), _ptr(gUnext), _ptr(gUn)))
+            return gUn
+        S = int(self.prob.rk)
+        if len(stages) != S - 1:
+            raise ValueError(f"{S - 1} stage inputs expected, got {len(stages)}")
+        arr = (C.c_void_p * (S - 1))(*[_ptr(t) for t in stages])
+        self._check(self._L.hydro_step_vjp_stages(self.ctx, _ptr(Un), arr, _ptr(d), _ptr(gUnext), _ptr(gUn)))
         return gUn
 
     def status(self):

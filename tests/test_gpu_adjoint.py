@@ -166,9 +166,11 @@ def test_turbulence_rollout_small():
     g_o = rollout_vjp(ost, tape_o, w)
     S = _solver(p)
     st = TorchStepper(S)
-    _, tape_g = rollout(st, S.to_device(p.U0), 10, 5)
-    assert tape_g.dts == tape_o.dts
+    # the forward pass keeps the last segment (CFL dts from hydro_cfl_dt)
+    _, tape_g = rollout(st, S.to_device(p.U0), 10, 5, keep_last=True)
+    assert tape_g.dts == tape_o.dts and sorted(tape_g.tail) == list(range(5, 10))
     g_g = rollout_vjp(st, tape_g, S.to_device(w)).cpu().numpy()
+    assert tape_g.recomputed_steps == 4
     assert_parity(p, g_g, g_o, "turb 64^3 rollout gradient")
     S.close()
 
@@ -221,4 +223,45 @@ def test_random_problems_step_vjp(k):
     S = _solver(p, **tune)
     got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
     assert_parity(p, got, ref, f"random vjp {k}")
+    S.close()
+
+
+def _kept_vs_recomputed(p, S, seed):
+    from paper_2401_03378_amd._hip import HydroError
+    dt = O.cfl_dt(p, p.U0)
+    Ug = S.to_device(p.U0)
+    U_before = Ug.clone()
+    m = torch.as_tensor(W.interior_mask(p.blocks, p.ncell, p.ndim), device=Ug.device)
+    UN, stages = S.step_keep(Ug, dt)
+    assert len(stages) == p.rk - 1
+    assert torch.equal(torch.nan_to_num(Ug), torch.nan_to_num(U_before))     # input left as it was
+    Ustep = Ug.clone()
+    S.step(Ustep, dt)
+    assert torch.equal(UN[:, m], Ustep[:, m])                                # the same step, bit for bit
+    g = S.to_device(_rand_cot(p, seed))
+    kept = S.step_vjp(Ug, g, dt, stages=stages)
+    rec = S.step_vjp(Ug, g, dt)
+    S.status()
+    assert torch.equal(kept, rec)
+    # argument checks of the entry point
+    with pytest.raises(HydroError):
+        S.step_vjp(Ug, g, dt, gUn=stages[0], stages=stages)
+    with pytest.raises(ValueError):
+        S.step_vjp(Ug, g, dt, stages=stages + [stages[0]])
+
+
+@pytest.mark.parametrize("ndim,recon,rk,n,ng,bc,NB", [SMALL[i] for i in (0, 2, 5, 6, 9)])
+def test_step_vjp_with_kept_stage_inputs(ndim, recon, rk, n, ng, bc, NB):
+    """hydro_step_vjp_stages fed the stage inputs of step_keep (hydro_rk_stage
+    stage by stage) gives hydro_step_vjp's result bit for bit."""
+    p = W.random_blocks(ndim, n, ng, seed=5, recon=recon, rk=rk, bc=bc, NB=NB)
+    S = _solver(p)
+    _kept_vs_recomputed(p, S, 12)
+    S.close()
+
+
+def test_step_vjp_with_kept_stage_inputs_sedov_full_size():
+    p = W.config(1)
+    S = _solver(p, **(_bench_tuning(p) or {}))
+    _kept_vs_recomputed(p, S, 13)
     S.close()

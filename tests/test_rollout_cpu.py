@@ -47,3 +47,62 @@ def test_rollout_gradient_matches_complex_step():
     a = np.sum(w[m] * jv[m])
     b = np.sum(g[m] * v[m])
     assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+class _KeepingStepper(OracleStepper):
+    """A stepper whose step_keep hands back what it was given, so that the
+    rollout's pairing of kept data with steps can be checked."""
+
+    def __init__(self, prob):
+        super().__init__(prob)
+        self.used = 0
+
+    def step_keep(self, Un, dt=None):
+        U = Un.copy()
+        dt = O.step(self.p, U, dt)
+        return U, (Un.copy(), dt), dt
+
+    def step_vjp(self, Un, g, dt, kept=None):
+        if kept is not None:
+            assert np.array_equal(kept[0], Un, equal_nan=True) and kept[1] == dt
+            self.used += 1
+        return super().step_vjp(Un, g, dt)
+
+
+@pytest.mark.parametrize("k", [1, 3, 4, 7])
+def test_kept_stage_data_reaches_the_vjp_of_its_own_step(k):
+    p = W.kh2d(N=32, n=8, nsteps=7)
+    m = W.interior_mask(p.blocks, p.ncell, 2)
+    plain, keeping = OracleStepper(p), _KeepingStepper(p)
+    UN, tape = rollout(plain, p.U0, 7, k)
+    UNk, tapek = rollout(keeping, p.U0, 7, k)
+    assert np.array_equal(UN[:, m], UNk[:, m])
+    g = _loss_grad(p, UN, p.U0.copy(), m)
+    ck = {n: c.copy() for n, c in tapek.checkpoints.items()}
+    assert np.array_equal(rollout_vjp(plain, tape, g), rollout_vjp(keeping, tapek, g))
+    # every recomputed step hands its kept data to its own VJP; the last step
+    # of each segment has none; checkpoints are left as they were
+    assert keeping.used == tapek.recomputed_steps == sum(min(k, 7 - s) - 1 for s in range(0, 7, k))
+    assert all(np.array_equal(ck[n], tapek.checkpoints[n], equal_nan=True) for n in ck)
+
+
+@pytest.mark.parametrize("k,nsteps", [(1, 7), (3, 7), (4, 8), (7, 7), (10, 7)])
+def test_last_segment_kept_by_the_forward_pass(k, nsteps):
+    p = W.kh2d(N=32, n=8, nsteps=nsteps)
+    m = W.interior_mask(p.blocks, p.ncell, 2)
+    plain, keeping = OracleStepper(p), _KeepingStepper(p)
+    UN, tape = rollout(plain, p.U0, nsteps, k)
+    UNk, tapek = rollout(keeping, p.U0, nsteps, k, keep_last=True)
+    assert np.array_equal(UN[:, m], UNk[:, m]) and tape.dts == tapek.dts
+    last = ((nsteps - 1) // k) * k
+    assert sorted(tapek.tail) == list(range(last, nsteps))
+    g = _loss_grad(p, UN, p.U0.copy(), m)
+    ref = rollout_vjp(plain, tape, g)
+    assert np.array_equal(ref, rollout_vjp(keeping, tapek, g))
+    # the last segment is not recomputed and all its steps use kept data
+    segs = [(s, min(s + k, nsteps)) for s in range(0, nsteps, k)]
+    assert tapek.recomputed_steps == sum(s1 - s0 - 1 for s0, s1 in segs[:-1])
+    assert keeping.used == tapek.recomputed_steps + (nsteps - last)
+    # the kept segment is used once; a second backward pass recomputes it
+    assert tapek.tail == {}
+    assert np.array_equal(ref, rollout_vjp(keeping, tapek, g))
