@@ -646,6 +646,19 @@ int setup_vjp(hydro_ctx *c)
                     ci.push_back(w);
                 }
     }
+    // One workgroup per item, dealt round-robin onto the 8 XCDs by index.
+    // Consecutive items are the row tiles of one plane run; they share the
+    // cache lines of the transposed x-line array (rows of ny doubles) and
+    // the lines that padded rows straddle.  Interleave each group of 32
+    // items so that every 4 consecutive ones get indices 8 apart: the same
+    // XCD, hence one L2.  Items are independent; only their order changes.
+    {
+        std::vector<WorkItem> o(ci.size());
+        const size_t full = ci.size() / 32 * 32;
+        for (size_t q = 0; q < ci.size(); ++q)
+            o[q < full ? (q / 32) * 32 + (q % 4) * 8 + (q % 32) / 4 : q] = ci[q];
+        ci.swap(o);
+    }
     c->ncitems = (int)ci.size();
     HIP_TRY(c, hipMalloc(&c->d_citems, sizeof(WorkItem) * std::max<size_t>(1, ci.size())));
     if (!ci.empty())
