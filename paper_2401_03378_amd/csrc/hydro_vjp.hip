@@ -32,13 +32,25 @@ namespace hydro {
 
 // ------------------------------------------------------- point-wise VJPs
 
-// Reverse of the wave-speed part of a face state: c = sqrt(gamma p r),
-// r = 1/rho, given cotangents gc and gr.
-__device__ __forceinline__ void wave_vjp(const double (&w)[5], double gc, double gr, double (&gW)[5], const Consts &K)
+// 1/x for the derivative arithmetic, which is held to a tolerance, not to the
+// forward's bits (values that decide a branch keep correctly rounded
+// divisions): the hardware reciprocal estimate refined by two Newton-Raphson
+// steps, r <- r + r (1 - x r), each of which squares the relative error.
+// Finite non-zero x of moderate exponent only (physical states).
+__device__ __forceinline__ double rcp_nr(double x)
 {
-    const double rho = w[0], p = w[4];
-    const double r = 1.0 / rho, c = sqrt((K.gamma * p) * r);
-    const double gx = gc / (2.0 * c);
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Reverse of the wave-speed part of a face state: c = sqrt(gamma p r),
+// r = 1/rho (both as the forward computed them), given cotangents gc and gr.
+__device__ __forceinline__ void wave_vjp(const double (&w)[5], double r, double c, double gc, double gr,
+                                         double (&gW)[5], const Consts &K)
+{
+    const double p = w[4];
+    const double gx = gc * rcp_nr(2.0 * c);
     gW[4] += gx * K.gamma * r;
     const double grt = gr + gx * K.gamma * p;
     gW[0] += -r * r * grt;
@@ -141,8 +153,9 @@ __device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&W
     }
     const double SK = right ? SR : SL, mK = right ? mR : mL, rK = right ? rR : rL;
     const double uK = W[1 + N];
-    const double den = SK - Ss, chi = mK / den;
-    const double q = W[4] / mK;
+    // chi and q enter only derivatives: reciprocals, not divisions
+    const double den = SK - Ss, iden = rcp_nr(den), imK = rcp_nr(mK), chi = mK * iden;
+    const double q = W[4] * imK;
     const double Bq = UK[NV - 1] * rK + (Ss - uK) * (Ss + q);
     double Us[5];
     Us[0] = chi;
@@ -171,10 +184,10 @@ __device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&W
     gSs += gB * (Ss + q) + gB * (Ss - uK);
     gWK[1 + N] -= gB * (Ss + q);
     const double gq = gB * (Ss - uK);
-    gWK[4] += gq / mK;
-    double gmK = -gq * q / mK;
-    gmK += gchi / den;
-    const double gden = -gchi * chi / den;
+    gWK[4] += gq * imK;
+    double gmK = -gq * q * imK;
+    gmK += gchi * iden;
+    const double gden = -gchi * chi * iden;
     gSK += gden;
     gSs -= gden;
     cons_flux_vjp<NDIM, N>(W, gUK, gF, gWK, K);          // F_K + terms through U_K
@@ -188,7 +201,8 @@ __device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&W
 #pragma unroll
         for (int v = 0; v < 5; ++v) gWL[v] += gWK[v];
     }
-    const double gN = gSs / Den, gD = -gSs * Ss / Den;
+    const double iDen = rcp_nr(Den);
+    const double gN = gSs * iDen, gD = -gSs * Ss * iDen;
     gWR[4] += gN;
     gWL[4] -= gN;
     gmL += gN * uL + gD;
@@ -204,8 +218,8 @@ __device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&W
     if (srR) { guR += gSR; gcR += gSR; } else { guL += gSR; gcL += gSR; }
     gWL[1 + N] += guL;
     gWR[1 + N] += guR;
-    wave_vjp(WL, gcL, grL, gWL, K);
-    wave_vjp(WR, gcR, grR, gWR, K);
+    wave_vjp(WL, rL, cL, gcL, grL, gWL, K);
+    wave_vjp(WR, rR, cR, gcR, grR, gWR, K);
 }
 
 // Reverse of the limited linear slope of (qa, q0, qb): adds to g[0..2].
@@ -231,7 +245,8 @@ __device__ __forceinline__ void plm_vjp(double qa, double q0, double qb, double 
 __device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gqp, double *g)
 {
     // Forward: s_k = (eps + beta_k)^2, o_k = product of the two other s_j,
-    // face value = sum(d_k o_k p_k) / sum(d_k o_k).  One reciprocal per face.
+    // face value = sum(d_k o_k p_k) / sum(d_k o_k).  One reciprocal per face
+    // (the face value is recomputed here for its derivatives only).
     const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
     const double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
     double t[3], w[3], sq[3], s[3];
@@ -253,7 +268,7 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gq
         const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;
         const double p2 = ((2.0 * c + 5.0 * d) - e) * k6;
         const double a0 = 0.1 * o[0], a1 = 0.6 * o[1], a2 = 0.3 * o[2];
-        const double iS = 1.0 / ((a0 + a1) + a2);
+        const double iS = rcp_nr((a0 + a1) + a2);
         const double gS = gqp * iS;
         const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
         const double gp0 = gS * a0, gp1 = gS * a1, gp2 = gS * a2;
@@ -271,7 +286,7 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gq
         const double p1 = ((-d + 5.0 * c) + 2.0 * b) * k6;
         const double p2 = ((2.0 * c + 5.0 * b) - a) * k6;
         const double a0 = 0.1 * o[2], a1 = 0.6 * o[1], a2 = 0.3 * o[0];
-        const double iS = 1.0 / ((a0 + a1) + a2);
+        const double iS = rcp_nr((a0 + a1) + a2);
         const double gS = gqm * iS;
         const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
         const double gp0 = gS * a0, gp1 = gS * a1, gp2 = gS * a2;
