@@ -53,7 +53,8 @@ def rollout(stepper, U0, nsteps, k, dts=None, keep_last=False):
             # out of place from here on: U itself is the checkpoint
             if n == last:
                 tape.checkpoints[n] = U
-            Unext, aux, dt = keep(U, dtn)
+            # the returned state takes its guard cells from U0, as in place
+            Unext, aux, dt = keep(U, dtn, stepper.copy(U) if n == nsteps - 1 else None)
             tape.tail[n] = (U, aux)
             U = Unext
         else:
@@ -67,7 +68,8 @@ def rollout(stepper, U0, nsteps, k, dts=None, keep_last=False):
 def rollout_vjp(stepper, tape, gUN):
     """Cotangent of U0 given the cotangent of U_N, by segments in reverse.
 
-    A stepper with step_keep(Un, dt) -> (U^{n+1}, kept, dt) recomputes a
+    A stepper with step_keep(Un, dt, out=None) -> (U^{n+1}, kept, dt)
+    (U^{n+1} in out if given, else in a new state) recomputes a
     segment's steps out of place and keeps what step_vjp(Un, g, dt, kept)
     would otherwise recompute (the stage inputs); the last step of a segment
     is not recomputed forward, so its VJP recomputes its own (except in a
@@ -124,10 +126,10 @@ class TorchStepper:
         d = self.S.step(U, dt)
         return float(d.item()) if torch.is_tensor(d) else float(d)
 
-    def step_keep(self, Un, dt=None):
+    def step_keep(self, Un, dt=None, out=None):
         if dt is None:
             dt = float(self.S.cfl_dt(Un).item())
-        Unext, stages = self.S.step_keep(Un, dt)
+        Unext, stages = self.S.step_keep(Un, dt, out)
         return Unext, stages, dt
 
     def step_vjp(self, Un, g, dt, stages=None):

@@ -273,6 +273,34 @@ void build_tables(hydro_ctx *c)
     }
 }
 
+// Order a list of independent work items (in block order) for a launch of
+// one workgroup per item, which the hardware deals round-robin onto the 8
+// XCDs by workgroup index: each XCD gets a contiguous range of whole blocks,
+// about an eighth of the items, and the 8 ranges are interleaved item by
+// item.  A block's items then share one L2, and so do most neighbouring
+// blocks (adjacent indices), whose halo lines the items read.  Only the
+// order changes, so results do not.
+void interleave_block_ranges(std::vector<WorkItem> &xi)
+{
+    std::vector<std::vector<WorkItem>> lane(8);
+    const size_t n = xi.size();
+    size_t q = 0;
+    for (int l = 0; l < 8; ++l) {
+        const size_t end = n * (size_t)(l + 1) / 8;
+        // past the lane's share only to finish the block in hand
+        while (q < n && (q < end || (!lane[l].empty() && xi[q].block == xi[q - 1].block)))
+            lane[l].push_back(xi[q++]);
+    }
+    std::vector<WorkItem> o;
+    o.reserve(n);
+    size_t maxl = 0;
+    for (auto &l : lane) maxl = std::max(maxl, l.size());
+    for (size_t r = 0; r < maxl; ++r)
+        for (int l = 0; l < 8; ++l)
+            if (r < lane[l].size()) o.push_back(lane[l][r]);
+    xi.swap(o);
+}
+
 int tile_x(int t) { return t == 0 ? 8 : 16; }
 int tile_y(int t) { return t == 2 ? 16 : 8; }
 
@@ -646,19 +674,10 @@ int setup_vjp(hydro_ctx *c)
                     ci.push_back(w);
                 }
     }
-    // One workgroup per item, dealt round-robin onto the 8 XCDs by index.
-    // Consecutive items are the row tiles of one plane run; they share the
-    // cache lines of the transposed x-line array (rows of ny doubles) and
-    // the lines that padded rows straddle.  Interleave each group of 32
-    // items so that every 4 consecutive ones get indices 8 apart: the same
-    // XCD, hence one L2.  Items are independent; only their order changes.
-    {
-        std::vector<WorkItem> o(ci.size());
-        const size_t full = ci.size() / 32 * 32;
-        for (size_t q = 0; q < ci.size(); ++q)
-            o[q < full ? (q / 32) * 32 + (q % 4) * 8 + (q % 32) / 4 : q] = ci[q];
-        ci.swap(o);
-    }
+    // The row tiles of one plane run share the cache lines of the transposed
+    // x-line array (rows of ny doubles) and the lines that padded rows
+    // straddle; guard copies read the neighbouring blocks' arrays.
+    interleave_block_ranges(ci);
     c->ncitems = (int)ci.size();
     HIP_TRY(c, hipMalloc(&c->d_citems, sizeof(WorkItem) * std::max<size_t>(1, ci.size())));
     if (!ci.empty())
@@ -680,6 +699,8 @@ int setup_vjp(hydro_ctx *c)
                         xi.push_back(w);
                     }
         }
+        // a tile reads its x halo from the neighbouring blocks
+        interleave_block_ranges(xi);
         c->nxitems = (int)xi.size();
         HIP_TRY(c, hipMalloc(&c->d_xitems, sizeof(WorkItem) * std::max<size_t>(1, xi.size())));
         if (!xi.empty())

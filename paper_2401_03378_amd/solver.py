@@ -123,20 +123,22 @@ class Solver:
             return dt
         return torch.full((1,), float(dt), dtype=torch.float64, device=self.device)
 
-    def step_keep(self, Un, dt):
+    def step_keep(self, Un, dt, out=None):
         """One step at dt out of place, stage by stage (hydro_rk_stage):
         returns (U^{n+1}, [U_2 .. U_S]), the stage inputs as step_vjp takes
-        them.  Un is not changed."""
+        them.  Un is not changed.  U^{n+1} is written into the interior of
+        out if given (its guard cells are left as they are), else into a new
+        tensor whose guard cells are unspecified, as are the stage inputs'."""
         d = self._dt_tensor(dt)
         S = int(self.prob.rk)
         stages = []
         Us = Un
         for s in range(1, S):
-            out = torch.empty_like(Un)
-            self.rk_stage(s, Un, Us, out, d)
-            stages.append(out)
-            Us = out
-        Unext = torch.empty_like(Un)
+            buf = torch.empty_like(Un)
+            self.rk_stage(s, Un, Us, buf, d)
+            stages.append(buf)
+            Us = buf
+        Unext = torch.empty_like(Un) if out is None else out
         self.rk_stage(S, Un, Us, Unext, d)
         return Unext, stages
 

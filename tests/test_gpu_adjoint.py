@@ -167,8 +167,13 @@ def test_turbulence_rollout_small():
     S = _solver(p)
     st = TorchStepper(S)
     # the forward pass keeps the last segment (CFL dts from hydro_cfl_dt)
-    _, tape_g = rollout(st, S.to_device(p.U0), 10, 5, keep_last=True)
+    U0 = S.to_device(p.U0)
+    UN, tape_g = rollout(st, U0, 10, 5, keep_last=True)
     assert tape_g.dts == tape_o.dts and sorted(tape_g.tail) == list(range(5, 10))
+    # U_N has U0's guard cells, as with steps in place
+    gm = torch.as_tensor(~W.interior_mask(p.blocks, p.ncell, p.ndim), device=U0.device)
+    assert torch.equal(UN[:, gm].isnan(), U0[:, gm].isnan())
+    assert torch.equal(torch.nan_to_num(UN[:, gm]), torch.nan_to_num(U0[:, gm]))
     g_g = rollout_vjp(st, tape_g, S.to_device(w)).cpu().numpy()
     assert tape_g.recomputed_steps == 4
     assert_parity(p, g_g, g_o, "turb 64^3 rollout gradient")
