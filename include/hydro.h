@@ -215,7 +215,10 @@ int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
  * step at Un): gUn = (dU^{n+1}/dU^n)^T gUnext over interior cells; the
  * padding of gUn is set to 0.  gUn must not alias gUnext.  It recomputes the
  * stage inputs from Un (no tape), is asynchronous, and is deterministic (no
- * atomics; linear in gUnext bit for bit).  The first call allocates the
+ * atomics; linear in gUnext bit for bit).  It equals the exact transpose up
+ * to rounding (summation order and reciprocal-based quotients in the
+ * derivative arithmetic; relative error near 1e-15 per field), not bit for
+ * bit.  The first call allocates the
  * ctx's adjoint scratch, (ndim x line segments + 4) x nvar x ncell_total
  * doubles, kept until hydro_destroy (HYDRO_ENOMEM if it cannot). */
 int hydro_step_vjp(hydro_ctx_t *ctx, const double *Un, const double *dt_dev,
