@@ -113,9 +113,14 @@ typedef struct {
 } hydro_amr_t;
 
 /* Launch configuration of the stage kernels (chosen by an autotuner). */
-#define HYDRO_MODE_PERSISTENT 0  /* one launch per stage over all blocks */
+#define HYDRO_MODE_PERSISTENT 0  /* one launch per stage over all blocks; guards gathered on load */
 #define HYDRO_MODE_PERBLOCK 1    /* per block: guard-fill launch + stage launch */
 #define HYDRO_MODE_TELESCOPING 2 /* one thick guard fill per step, stages on the extended blocks */
+#define HYDRO_MODE_MATERIALISED 3 /* one guard-fill launch over all blocks + one stage launch */
+/* In the per-block and materialised modes a stage first writes the guard
+ * cells of its input state (the paper's per-stage fill), so hydro_step and
+ * hydro_rk_stage then write the guard cells of U and Us; the interiors they
+ * produce are the same bit for bit in every mode. */
 typedef struct {
     int32_t mode;       /* HYDRO_MODE_* */
     int32_t tile;       /* xy tile of a work item: 0 = 8x8, 1 = 16x8, 2 = 16x16 */
@@ -187,8 +192,9 @@ int hydro_cfl_dt(hydro_ctx_t *ctx, const double *U, double *dt_dev);
 /* One SSP-RK stage s (1-based):  T = Us + dt L(Us);  Uout = T for s = 1,
  * else Uout = b_s T + a_s Un with (a,b) = (1/2,1/2) [RK2], (3/4,1/4) and
  * (1/3,2/3) [RK3].  Reads the interiors of Un and Us (guards are gathered
- * from their sources), writes the interior of Uout.  Uout may alias Un, not
- * Us.  dt is read from dt_dev on the device. */
+ * from their sources; in the per-block and materialised modes they are
+ * first written into Us's guard cells), writes the interior of Uout.  Uout
+ * may alias Un, not Us.  dt is read from dt_dev on the device. */
 int hydro_rk_stage(hydro_ctx_t *ctx, int32_t stage, const double *dt_dev,
                    const double *Un, const double *Us, double *Uout);
 
@@ -201,7 +207,7 @@ int hydro_rk_stage(hydro_ctx_t *ctx, int32_t stage, const double *dt_dev,
  * caller must not write U's interior between the two calls by other means
  * than this library (the ctx forgets the maxima on hydro_rk_stage,
  * hydro_set_tuning, any other hydro_step call or a different U, and then
- * reads U as with 1).  It applies to the persistent mode on meshes without
+ * reads U as with 1).  It applies to HYDRO_MODE_PERSISTENT on meshes without
  * levels; elsewhere it acts as 1.  With use_graph, the step is captured into
  * a hipGraph bound to (U, dt_dev, dt mode) once the same arguments arrive in
  * two consecutive calls, and replayed while they stay the same; other calls

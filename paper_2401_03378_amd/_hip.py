@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libhydro.so")
 
 HYDRO_OK, HYDRO_EINVAL, HYDRO_EHIP, HYDRO_ENONPHYS, HYDRO_ENOMEM = 0, -1, -2, -3, -4
-MODE_PERSISTENT, MODE_PERBLOCK = 0, 1
+MODE_PERSISTENT, MODE_PERBLOCK, MODE_TELESCOPING, MODE_MATERIALISED = 0, 1, 2, 3
 TILES = {0: (8, 8), 1: (16, 8), 2: (16, 16)}
 
 EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create_amr",

@@ -126,9 +126,12 @@ def tuned_or_search(S, prob, log=print, cache=None):
     return best
 
 
-def compare_forms(indices, log=print):
+def compare_forms(indices, log=print, perblock=True):
     """For each named workload: the tuned persistent form (searched, or taken
-    from the cache) against the plain per-block launch form, as JSON lines."""
+    from the cache; guards gathered on load) against the same launch
+    configuration with one materialised guard-fill launch per stage, and
+    against the plain per-block launch form (unless perblock is false), as
+    JSON lines."""
     from . import workloads as W
     from .solver import Solver
 
@@ -147,11 +150,15 @@ def compare_forms(indices, log=print):
         best = tuned_or_search(S, p, log=log)
         U0 = S.to_device(p.U0)
         t_best = timeit(S, U0, 5, 2)
-        S.set_tuning(mode=1, use_graph=0)
-        t_pb = timeit(S, U0, 2 if ci in (2, 4) else 5, 1)
+        S.set_tuning(**dict(best, mode=3))
+        t_mat = timeit(S, U0, 5, 2)
         z = p.interior_zones * p.rk
-        r = dict(cfg=ci, name=p.name, tuned=best, ms_step_tuned=t_best * 1e3, ms_step_perblock=t_pb * 1e3,
-                 speedup=t_pb / t_best, zus_tuned=z / t_best, zus_perblock=z / t_pb)
+        r = dict(cfg=ci, name=p.name, tuned=best, ms_step_tuned=t_best * 1e3, ms_step_materialised=t_mat * 1e3,
+                 gather_over_materialised=t_mat / t_best, zus_tuned=z / t_best, zus_materialised=z / t_mat)
+        if perblock:
+            S.set_tuning(mode=1, use_graph=0)
+            t_pb = timeit(S, U0, 2 if ci in (2, 4) else 5, 1)
+            r.update(ms_step_perblock=t_pb * 1e3, speedup=t_pb / t_best, zus_perblock=z / t_pb)
         print(json.dumps(r), flush=True)
         out.append(r)
     return out
@@ -190,5 +197,7 @@ if __name__ == "__main__":
     quiet = dict(log=lambda *a: print(*a, file=sys.stderr, flush=True))
     if args and args[0] == "--telescoping":
         compare_telescoping([int(a) for a in args[1:]] or [0, 1, 2, 3, 4], **quiet)
+    elif args and args[0] == "--no-perblock":
+        compare_forms([int(a) for a in args[1:]] or [0, 1, 2, 3, 4], perblock=False, **quiet)
     else:
         compare_forms([int(a) for a in args] or [0, 1, 2, 3, 4], **quiet)

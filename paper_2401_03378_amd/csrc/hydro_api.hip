@@ -550,12 +550,24 @@ int enqueue_guards(hydro_ctx *c, double *U, int b0, int nblk, hipStream_t st)
     return HYDRO_OK;
 }
 
-// One stage in the configured form.  In per-block form Us must be writable
-// (its guards are materialised block by block).
+// One stage in the configured form.  In the per-block and materialised
+// forms Us must be writable (its guard cells are filled before the stage
+// kernel reads them, block by block or in one launch).
 int enqueue_stage(hydro_ctx *c, int s, const double *dt, const double *Un, const double *Us, double *Uout,
                   hipStream_t st, double *cflo = nullptr)
 {
     StageArgs a = stage_args(c, s, dt, Un, Us, Uout);
+    if (c->tune.mode == HYDRO_MODE_MATERIALISED) {
+        // one fill launch over every block, then the persistent stage launch
+        // reading the filled guard cells (the stage's CFL record needs the
+        // gathering kernel, so cflo is never set in this form)
+        int rc = enqueue_guards(c, const_cast<double *>(Us), 0, c->nblocks, st);
+        if (rc) return rc;
+        hipError_t e = launch_stage(a, c->prm.ndim, c->prm.recon, c->tune.tile, c->tune.variant, false,
+                                    persistent_grid(c), st);
+        if (e != hipSuccess) return hip_fail(c, e, "stage launch");
+        return HYDRO_OK;
+    }
     if (c->tune.mode == HYDRO_MODE_PERBLOCK) {
         for (int b = 0; b < c->nblocks; ++b) {
             int rc = enqueue_guards(c, const_cast<double *>(Us), b, 1, st);
@@ -1093,7 +1105,8 @@ int hydro_create_amr(const hydro_params_t *params, const hydro_block_t *blocks, 
 int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
 {
     if (!c || !t) return HYDRO_EINVAL;
-    if (t->mode != HYDRO_MODE_PERSISTENT && t->mode != HYDRO_MODE_PERBLOCK && t->mode != HYDRO_MODE_TELESCOPING)
+    if (t->mode != HYDRO_MODE_PERSISTENT && t->mode != HYDRO_MODE_PERBLOCK && t->mode != HYDRO_MODE_TELESCOPING &&
+        t->mode != HYDRO_MODE_MATERIALISED)
         return fail(c, HYDRO_EINVAL, "mode");
     if (t->tile < 0 || t->tile > 2 || t->grid < 0 || t->zchunk < 0 || t->variant < 0 || t->variant > 1 ||
         t->xcd < 0 || t->xcd > 2)

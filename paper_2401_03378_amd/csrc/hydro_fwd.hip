@@ -642,7 +642,9 @@ __global__ void __launch_bounds__(256) k_amr_correct(AmrArgs A)
 }
 
 // Materialised guard fill for blocks [b0, b0 + gridDim.x / (2 NDIM)):
-// workgroup = (block, face); threads walk layers x transverse cells.
+// workgroup = (block, face); threads walk layers x transverse cells with the
+// index that is contiguous in memory fastest: the layer on x faces (the ng
+// guard cells of a row), the x index on y and z faces.
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_fill_guards(GuardArgs A)
 {
@@ -656,8 +658,9 @@ __global__ void __launch_bounds__(256) k_fill_guards(GuardArgs A)
     const int n2 = (NDIM == 3) ? ((d == 2) ? B.ny : B.nz) : 1;
     const int count = B.ng * n1 * n2;
     for (int e = threadIdx.x; e < count; e += blockDim.x) {
-        const int l = e / (n1 * n2) + 1;
-        const int r = e % (n1 * n2);
+        int l, r;
+        if (d == 0) { l = e % B.ng + 1; r = e / B.ng; }
+        else { l = e / (n1 * n2) + 1; r = e % (n1 * n2); }
         const int e1 = r % n1, e2 = r / n1;
         const int pos = (side == 0) ? -l : n - 1 + l;
         const int sp = S.A + S.B * pos;

@@ -160,10 +160,13 @@ def test_turbulence_small_all_steps():
 
 @pytest.mark.parametrize("mode_kw", [dict(mode=1), dict(use_graph=0), dict(grid=37), dict(grid=256, xcd=1),
                                      dict(xcd=2), dict(grid=512, xcd=2, zchunk=4),
-                                     dict(variant=1), dict(mode=1, variant=1)])
+                                     dict(variant=1), dict(mode=1, variant=1),
+                                     dict(mode=3), dict(mode=3, use_graph=0, variant=1),
+                                     dict(mode=3, tile=0, grid=37)])
 def test_launch_forms_bitwise_identical(mode_kw):
-    """Per-block launches, no graph, odd persistent grids and the XCD
-    placement all give the persistent graph-replayed result bit for bit."""
+    """Per-block launches, one materialised fill per stage, no graph, odd
+    persistent grids and the XCD placement all give the persistent
+    graph-replayed result bit for bit."""
     p = W.batched_uneven(nblocks=96, seed=4)
     ref, dref = _gpu_run(p, 3)
     Ug, dtg = _gpu_run(p, 3, **mode_kw)
@@ -199,6 +202,28 @@ def test_fill_guards_matches_oracle():
     S = _solver(p)
     U = S.to_device(p.U0)
     S.fill_guards(U)
+    ref = p.U0.copy()
+    O.fill_guards(p, ref)
+    got = U.cpu().numpy()
+    both_nan = np.isnan(got) & np.isnan(ref)
+    assert np.array_equal(got[~both_nan], ref[~both_nan]) and np.array_equal(np.isnan(got), np.isnan(ref))
+    S.close()
+
+
+def test_materialised_stage_fills_the_input_guards():
+    """HYDRO_MODE_MATERIALISED: a stage writes the guard cells of its input
+    as the oracle's fill does, and its output is the gathering form's."""
+    p = W.random_blocks(3, 6, 3, seed=6, bc="outflow", NB=(2, 1, 3))
+    S = _solver(p)
+    U = S.to_device(p.U0)
+    dt = S.cfl_dt(U)
+    ref_out = U.clone()
+    S.rk_stage(1, U, U, ref_out)
+    S.set_tuning(mode=3)
+    out = U.clone()
+    S.rk_stage(1, U, U, out)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    assert torch.equal(out[:, m], ref_out[:, m])
     ref = p.U0.copy()
     O.fill_guards(p, ref)
     got = U.cpu().numpy()
@@ -406,3 +431,15 @@ def test_random_problems_bit_for_bit(ndim, recon, rk, n, ng, bc, NB, amp, seed, 
     Ug, dtg = _gpu_run(p, 3, **tune)
     assert np.array_equal(dtg, dto)
     assert_parity(p, Ug, Uo, f"random {ndim}d recon {recon} n {n} ng {ng} {bc} {NB} {tune}", bitwise=True)
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_materialised_mode_random_problems_bit_for_bit(k):
+    """The first eight random problems in HYDRO_MODE_MATERIALISED (one guard
+    fill launch per stage, then the non-gathering stage kernel)."""
+    ndim, recon, rk, n, ng, bc, NB, amp, seed, tune = RANDOM_CASES[k]
+    p = W.random_blocks(ndim, n, ng, seed, recon=recon, rk=rk, bc=bc, NB=NB, amp=amp)
+    Uo, dto = _ora_run(p, 3)
+    Ug, dtg = _gpu_run(p, 3, **dict(tune, mode=3))
+    assert np.array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, f"materialised random {k}", bitwise=True)
