@@ -169,6 +169,9 @@ int hydro_create_amr(const hydro_params_t *params, const hydro_block_t *blocks,
                      int64_t ncell_total, void *stream, hydro_ctx_t **out);
 
 /* Replace / read the launch configuration.  Invalidates captured graphs.
+ * HYDRO_EINVAL for a mode other than the four HYDRO_MODE_* values or a field
+ * out of range.  HYDRO_MODE_PERSISTENT, _PERBLOCK and _MATERIALISED give the
+ * same interiors bit for bit (the latter two write guard cells, see above).
  * HYDRO_MODE_TELESCOPING is the paper's telescoping RK variant (Sec. 4.2,
  * second RK listing): per step one guard fill into thick block copies with
  * S*(R+1) layers (R = 1 PLM, 2 WENO5; edges and corners included), then all
