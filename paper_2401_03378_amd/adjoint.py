@@ -137,21 +137,23 @@ class TorchStepper:
 
 
 class HydroStep(torch.autograd.Function):
-    """U_{n+1} = step(U_n) at a given dt; backward = hydro_step_vjp."""
+    """U_{n+1} = step(U_n) at a given dt, run stage by stage so that the
+    stage inputs are saved (S-1 states besides U_n); backward =
+    hydro_step_vjp_stages on them.  The output's guard cells are U_n's."""
 
     @staticmethod
     def forward(ctx, U, dt, solver):
-        out = U.detach().clone()
-        solver.step(out, float(dt))
-        ctx.save_for_backward(U.detach())
+        Un = U.detach()
+        out, stages = solver.step_keep(Un, float(dt), out=Un.clone())
+        ctx.save_for_backward(Un, *stages)
         ctx.dt = float(dt)
         ctx.solver = solver
         return out
 
     @staticmethod
     def backward(ctx, g):
-        (U,) = ctx.saved_tensors
-        return ctx.solver.step_vjp(U, g.contiguous(), ctx.dt), None, None
+        U, *stages = ctx.saved_tensors
+        return ctx.solver.step_vjp(U, g.contiguous(), ctx.dt, stages=list(stages)), None, None
 
 
 class HydroRollout(torch.autograd.Function):
