@@ -19,6 +19,8 @@ from __future__ import annotations
 
 import torch
 
+from . import _hip
+
 
 class Tape:
     """What a checkpointed forward rollout keeps: states every k steps and
@@ -144,7 +146,13 @@ class HydroStep(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U, dt, solver):
         Un = U.detach()
-        out, stages = solver.step_keep(Un, float(dt), out=Un.clone())
+        if solver.tuning()["mode"] == _hip.MODE_TELESCOPING:
+            # no single stages in this mode (and no VJP: backward raises)
+            out = Un.clone()
+            solver.step(out, float(dt))
+            stages = []
+        else:
+            out, stages = solver.step_keep(Un, float(dt), out=Un.clone())
         ctx.save_for_backward(Un, *stages)
         ctx.dt = float(dt)
         ctx.solver = solver
@@ -153,7 +161,7 @@ class HydroStep(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         U, *stages = ctx.saved_tensors
-        return ctx.solver.step_vjp(U, g.contiguous(), ctx.dt, stages=list(stages)), None, None
+        return ctx.solver.step_vjp(U, g.contiguous(), ctx.dt, stages=list(stages) or None), None, None
 
 
 class HydroRollout(torch.autograd.Function):

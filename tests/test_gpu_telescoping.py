@@ -73,4 +73,15 @@ def test_telescoping_mode_errors():
         S.rk_stage(1, U, U, U.clone())
     with pytest.raises(HydroError):
         S.step_vjp(U, U.clone(), 1e-3)
+    # the per-step autograd Function still steps forward in this mode (the
+    # telescoping step); its backward pass is refused like step_vjp
+    from paper_2401_03378_amd.adjoint import hydro_step
+    ref = U.clone()
+    S.step(ref, 1e-3)
+    x = U.clone().requires_grad_(True)
+    y = hydro_step(x, 1e-3, S)
+    m = torch.as_tensor(W.interior_mask(q.blocks, q.ncell, 2), device=U.device)
+    assert torch.equal(y.detach()[:, m], ref[:, m])
+    with pytest.raises(RuntimeError):        # HydroError, as raised through autograd
+        torch.nan_to_num(y).sum().backward()
     S.close()
