@@ -129,6 +129,8 @@ class Solver:
         them.  Un is not changed.  U^{n+1} is written into the interior of
         out if given (its guard cells are left as they are), else into a new
         tensor whose guard cells are unspecified, as are the stage inputs'."""
+        if out is not None and out.data_ptr() == Un.data_ptr():
+            raise ValueError("out must not alias Un (step_keep leaves Un as it is)")
         d = self._dt_tensor(dt)
         S = int(self.prob.rk)
         stages = []

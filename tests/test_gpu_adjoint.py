@@ -262,6 +262,8 @@ def _kept_vs_recomputed(p, S, seed):
         S.step_vjp(Ug, g, dt, gUn=stages[0], stages=stages)
     with pytest.raises(ValueError):
         S.step_vjp(Ug, g, dt, stages=stages + [stages[0]])
+    with pytest.raises(ValueError):
+        S.step_keep(Ug, dt, out=Ug)
 
 
 @pytest.mark.parametrize("ndim,recon,rk,n,ng,bc,NB", [SMALL[i] for i in (0, 2, 5, 6, 9)])
