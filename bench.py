@@ -125,6 +125,7 @@ def amr_extra(nsteps=10):
     updates per second of hydro_step (coarse-fine guard fill, stage, flux
     correction), with the all-levels and the level-by-level order."""
     import torch
+    from paper_2401_03378_amd import autotune
     from paper_2401_03378_amd import workloads as W
     from paper_2401_03378_amd.solver import Solver
     prob = W.amr_problem(3, NBc=(8, 8, 8), n=16, ng=3, recon=W.WENO5, rk=3, flow="blob",
@@ -133,8 +134,14 @@ def amr_extra(nsteps=10):
     res = {"workload": "two-level mesh: 448 coarse + 512 fine blocks of 16^3 (central 4^3 coarse blocks refined), "
                        "WENO5 + HLLC + SSP-RK3, flux correction at coarse-fine faces",
            "zones": zones}
+    tuning = None
     for lbl in (False, True):
         S = Solver(prob, level_by_level=lbl)
+        if tuning is None:    # the autotuner's choice for this mesh (all-levels order), cached
+            tuning = autotune.tuned_or_search(S, prob, log=lambda *a: None)
+            res["tuning"] = tuning
+        else:
+            S.set_tuning(**tuning)
         U0 = S.to_device(prob.U0)
         U = U0.clone()
         for _ in range(3):
