@@ -101,3 +101,12 @@ def test_fp_check_rejects_bad_arguments_without_a_gpu():
     L = _hip.lib()
     assert L.hydro_fp_check(None, None, None, None, None, None, -1, None) == _hip.HYDRO_EINVAL
     assert L.hydro_fp_check(None, None, None, None, None, None, 4, None) == _hip.HYDRO_EINVAL
+
+
+def test_step_vjp_stages_rejects_null_arguments_without_a_gpu():
+    """Argument checks come before any HIP call: a null ctx or a null stage
+    array is HYDRO_EINVAL on a host without a GPU."""
+    L = _hip.lib()
+    assert L.hydro_step_vjp_stages(None, None, None, None, None, None) == _hip.HYDRO_EINVAL
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.hydro_step_vjp_stages(None, None, arr, None, None, None) == _hip.HYDRO_EINVAL
