@@ -130,7 +130,8 @@ typedef struct {
     int32_t xcd;        /* 0: list order; 1: a block's work items on one XCD (L2), blocks
                            dealt round-robin; 2: the same with contiguous ranges of
                            block indices per XCD (neighbours share an L2) */
-    int32_t variant;    /* stage schedule: 0 plain, 1 loads of the next plane issued a plane ahead */
+    int32_t variant;    /* stage schedule: 0 plain, 1 loads of the next plane issued a plane ahead
+                           (meshes with levels always run the plain schedule) */
 } hydro_tuning_t;
 
 typedef struct hydro_ctx hydro_ctx_t;

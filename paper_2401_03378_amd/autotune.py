@@ -42,9 +42,11 @@ def candidates(prob, ncu):
     blocks first."""
     out = []
     zch = [0] if prob.ndim == 2 else [0, 8]
-    # a mesh with levels orders its work list by level; XCD placement is not used there
-    xcds = (0,) if getattr(prob, "amr", None) is not None else (2, 1, 0)
-    for variant in (0, 1):
+    # a mesh with levels orders its work list by level and runs the plain
+    # schedule: neither XCD placement nor the prefetching schedule applies
+    amr = getattr(prob, "amr", None) is not None
+    xcds = (0,) if amr else (2, 1, 0)
+    for variant in ((0,) if amr else (0, 1)):
         for tile in (2, 1, 0):
             for xcd in xcds:
                 for zc in zch:
