@@ -281,3 +281,24 @@ def test_step_vjp_with_kept_stage_inputs_sedov_full_size():
     S = _solver(p, **(_bench_tuning(p) or {}))
     _kept_vs_recomputed(p, S, 13)
     S.close()
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_rollout_gradient_in_materialising_modes(mode):
+    """Per-block and materialised modes write guard cells into the states the
+    rollout keeps; the gradient is the persistent mode's bit for bit."""
+    p = W.random_blocks(3, 8, 3, seed=9, recon=1, rk=3, bc="outflow", NB=(2, 2, 1))
+    w = _rand_cot(p, 9)
+    out = []
+    for md in (0, mode):
+        S = _solver(p, mode=md)
+        st = TorchStepper(S)
+        UN, tape = rollout(st, S.to_device(p.U0), 5, 2, keep_last=True)
+        g = rollout_vjp(st, tape, S.to_device(w))
+        S.status()
+        m = torch.as_tensor(W.interior_mask(p.blocks, p.ncell, 3), device=UN.device)
+        out.append((tape.dts, UN[:, m].clone(), g.clone()))
+        S.close()
+    assert out[0][0] == out[1][0]
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][2], out[1][2])
