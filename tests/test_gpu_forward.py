@@ -443,3 +443,14 @@ def test_materialised_mode_random_problems_bit_for_bit(k):
     Ug, dtg = _gpu_run(p, 3, **dict(tune, mode=3))
     assert np.array_equal(dtg, dto)
     assert_parity(p, Ug, Uo, f"materialised random {k}", bitwise=True)
+
+
+def test_materialised_mode_full_size_sedov():
+    """The Sedov 128^3 workload (the bench's) in HYDRO_MODE_MATERIALISED gives
+    the gathering form's states and dts bit for bit over three steps."""
+    p = W.config(1)
+    ref, dref = _gpu_run(p, 3)
+    Ug, dtg = _gpu_run(p, 3, mode=3)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    assert np.array_equal(dtg, dref)
+    assert np.array_equal(Ug[:, m], ref[:, m])
