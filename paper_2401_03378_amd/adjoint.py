@@ -125,7 +125,9 @@ class TorchStepper:
         return U.clone()
 
     def step(self, U, dt=None):
-        d = self.S.step(U, dt)
+        # a rollout steps one state in place: its CFL dt can come from the
+        # maxima the previous step recorded (the same dt, bit for bit)
+        d = self.S.step(U, dt, dt_from_previous=dt is None)
         return float(d.item()) if torch.is_tensor(d) else float(d)
 
     def step_keep(self, Un, dt=None, out=None):
