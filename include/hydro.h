@@ -80,6 +80,8 @@ typedef struct {
     double gamma;     /* ratio of specific heats, > 1 */
     double cfl;       /* Courant number of the unsplit sum, > 0 */
     double dx, dy, dz;  /* cell widths (dz ignored in 2D but must be > 0) */
+    double weno_eps;  /* epsilon of the WENO5 nonlinear weights alpha_k = d_k/(eps+beta_k)^2,
+                         finite and > 0 (Jiang & Shu 1996 use 1e-6); ignored by PLM-MC */
 } hydro_params_t;
 
 /* Refinement levels (hydro_create_amr).  Flash-X's block-structured AMR
@@ -138,7 +140,7 @@ typedef struct hydro_ctx hydro_ctx_t;
 
 /* Host-only check of a problem description (no GPU use).  Returns HYDRO_OK
  * or HYDRO_EINVAL: null pointer, ndim/recon/rk out of range, gamma <= 1,
- * cfl or dx <= 0, extents < 1, ng below the stencil's need, 2D block with
+ * cfl or dx <= 0, weno_eps not finite and > 0, extents < 1, ng below the stencil's need, 2D block with
  * nz != 1, offsets out of range or overlapping, link index out of range,
  * neighbour faces that do not match. */
 int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks,
@@ -189,11 +191,19 @@ int hydro_get_tuning(hydro_ctx_t *ctx, hydro_tuning_t *tuning);
 int hydro_fill_guards(hydro_ctx_t *ctx, double *U);
 
 /* CFL time step dt = cfl / max over interior cells of
- * sum_d (|u_d| + c) / dx_d, computed from U; written to dt_dev (one device
- * double).  Asynchronous. */
+ * sum_d (|u_d| + c) / dx_d (the unsplit wave-speed sum of every direction,
+ * sound speed c = sqrt(gamma p / rho)), computed from U; written to dt_dev
+ * (one device double).  The paper gives no time-step rule; this is the
+ * usual CFL bound of an explicit unsplit finite-volume step, taken once per
+ * step of Sec. 4.2's RK loop, before its stages.  Asynchronous. */
 int hydro_cfl_dt(hydro_ctx_t *ctx, const double *U, double *dt_dev);
 
-/* One SSP-RK stage s (1-based):  T = Us + dt L(Us);  Uout = T for s = 1,
+/* One SSP-RK stage s (1-based), the body of the stage loop of the paper's
+ * non-telescoping RK listing (Sec. 4.2): fill guard cells, then for every
+ * block the intra-stage chain of Algorithm "Intra stage calculations for
+ * Spark" (calcEos, calcLims, calcFlux, updSoln), here L(Us) = minus the flux
+ * differences of HLLC fluxes between reconstructed face states, combined as
+ * T = Us + dt L(Us);  Uout = T for s = 1,
  * else Uout = b_s T + a_s Un with (a,b) = (1/2,1/2) [RK2], (3/4,1/4) and
  * (1/3,2/3) [RK3].  Reads the interiors of Un and Us (guards are gathered
  * from their sources; in the per-block and materialised modes they are
@@ -202,28 +212,36 @@ int hydro_cfl_dt(hydro_ctx_t *ctx, const double *U, double *dt_dev);
 int hydro_rk_stage(hydro_ctx_t *ctx, int32_t stage, const double *dt_dev,
                    const double *Un, const double *Us, double *Uout);
 
-/* One full step in place on U.  If compute_dt != 0 the CFL dt of U is first
- * written to dt_dev; otherwise the value already in dt_dev is used.
- * compute_dt = HYDRO_DT_FROM_PREVIOUS gives the same dt, bit for bit, for a
- * caller that steps one state repeatedly: the final stage of such a step
- * also records the CFL maxima of the state it writes, and the next such
- * call on the same U takes dt from them instead of reading U again.  The
- * caller must not write U's interior between the two calls by other means
- * than this library (the ctx forgets the maxima on hydro_rk_stage,
- * hydro_set_tuning, any other hydro_step call or a different U, and then
- * reads U as with 1).  It applies to HYDRO_MODE_PERSISTENT on meshes without
- * levels; elsewhere it acts as 1.  With use_graph, the step is captured into
+/* One full step in place on U: the non-telescoping SSP-RK step of the
+ * paper's Sec. 4.2 (per stage: guard fill, then every block's intra-stage
+ * chain of Algorithm "Intra stage calculations for Spark"), preceded by the
+ * CFL time step.  If compute_dt != 0 the CFL dt of U is first written to
+ * dt_dev; otherwise the value already in dt_dev is used.
+ * compute_dt = HYDRO_DT_RECORD (3) computes the CFL dt from U as 1 does, and
+ * the final stage also records the CFL maxima of the state it writes;
+ * compute_dt = HYDRO_DT_FROM_PREVIOUS (2) then gives the next step of the
+ * same state the same dt, bit for bit, from those maxima instead of reading
+ * U again, and records again.  The ctx recognises "the same state" by its
+ * address only, so the caller must pass HYDRO_DT_FROM_PREVIOUS only for the
+ * very allocation the previous recording step wrote, not freed since, and
+ * must not have written its interior by other means than this library (the
+ * ctx itself forgets the maxima on hydro_rk_stage, hydro_set_tuning, any
+ * other hydro_step call or a different U, and then acts as with
+ * HYDRO_DT_RECORD).  Both apply to HYDRO_MODE_PERSISTENT on meshes without
+ * levels; elsewhere they act as 1.  With use_graph, the step is captured into
  * a hipGraph bound to (U, dt_dev, dt mode) once the same arguments arrive in
  * two consecutive calls, and replayed while they stay the same; other calls
  * launch the kernels directly.  Either way the result is the same bit for
  * bit. */
 #define HYDRO_DT_FROM_PREVIOUS 2
+#define HYDRO_DT_RECORD 3
 int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
 
 /* Vector-Jacobian product of one step with dt held fixed (the branch
  * decisions of limiters, fallback and Riemann solver are those of the forward
  * step at Un): gUn = (dU^{n+1}/dU^n)^T gUnext over interior cells; the
- * padding of gUn is set to 0.  gUn must not alias gUnext.  It recomputes the
+ * padding of gUn is set to 0.  gUn must alias neither gUnext nor Un
+ * (HYDRO_EINVAL: gUn is cleared before Un is read).  It recomputes the
  * stage inputs from Un (no tape), is asynchronous, and is deterministic (no
  * atomics; linear in gUnext bit for bit).  It equals the exact transpose up
  * to rounding (summation order and reciprocal-based quotients in the
@@ -244,7 +262,7 @@ int hydro_step_vjp(hydro_ctx_t *ctx, const double *Un, const double *dt_dev,
  * has just run the step stage by stage (a checkpointed rollout recomputing a
  * segment) it saves the S-1 stage launches; with those stage inputs the
  * result is bit for bit that of hydro_step_vjp.  HYDRO_EINVAL if stages or
- * one of its pointers is null or gUn aliases gUnext or a stage input. */
+ * one of its pointers is null or gUn aliases gUnext, Un or a stage input. */
 int hydro_step_vjp_stages(hydro_ctx_t *ctx, const double *Un, const double *const *stages,
                           const double *dt_dev, const double *gUnext, double *gUn);
 

@@ -20,6 +20,9 @@ import numpy as np
 from . import build as _build
 
 ORA_OK, ORA_EINVAL, ORA_ENONPHYS, ORA_ENOMEM = 0, -1, -3, -4
+# Epsilon of the WENO5 nonlinear weights in Jiang & Shu (1996); a problem may
+# carry its own (attribute weno_eps).
+WENO_EPS = 1e-6
 
 
 class OracleError(RuntimeError):
@@ -46,7 +49,7 @@ class _Problem(C.Structure):
                 ("nblocks", C.c_int32), ("ncell", C.c_int64),
                 ("gamma", C.c_double), ("cfl", C.c_double), ("dx", C.c_double),
                 ("dy", C.c_double), ("dz", C.c_double),
-                ("blocks", C.c_void_p), ("links", C.c_void_p)]
+                ("blocks", C.c_void_p), ("links", C.c_void_p), ("weno_eps", C.c_double)]
 
 
 _lib = None
@@ -73,16 +76,18 @@ def lib():
             "ora_cs_step": (C.c_int, [P, dp, dp, C.c_double]),
             "ora_eos_n": (C.c_int, [P, i64, dp, dp]),
             "ora_plm_n": (None, [i64, dp, dp, dp, ip]),
-            "ora_weno5_n": (None, [i64, dp, dp, dp]),
+            "ora_weno5_n": (None, [i64, dp, C.c_double, dp, dp]),
+            "ora_recon_cell_n": (None, [P, i64, dp, dp, dp, ip]),
+            "ora_faces": (C.c_int, [P, dp, C.c_int, dp, dp, ip]),
             "ora_hllc_n": (C.c_int, [P, i64, C.c_int, dp, dp, dp, ip]),
             "ora_state_flux_n": (None, [P, i64, C.c_int, dp, dp, dp, dp]),
             "ora_eos_vjp_n": (None, [P, i64, dp, dp, dp]),
             "ora_plm_vjp_n": (None, [i64, dp, dp, dp, dp]),
-            "ora_weno5_vjp_n": (None, [i64, dp, dp, dp, dp]),
+            "ora_weno5_vjp_n": (None, [i64, dp, C.c_double, dp, dp, dp]),
             "ora_hllc_vjp_n": (None, [P, i64, C.c_int, dp, dp, dp, dp, dp]),
             "ora_cs_eos_n": (None, [P, i64, dp, dp, dp, dp]),
             "ora_cs_plm_n": (None, [i64, dp, dp, dp, dp, dp, dp]),
-            "ora_cs_weno5_n": (None, [i64, dp, dp, dp, dp, dp, dp]),
+            "ora_cs_weno5_n": (None, [i64, dp, dp, C.c_double, dp, dp, dp, dp]),
             "ora_cs_hllc_n": (None, [P, i64, C.c_int, dp, dp, dp, dp, dp, dp]),
             "ora_amr_validate": (C.c_int, [P, C.c_void_p]),
             "ora_amr_fill_guards": (C.c_int, [P, C.c_void_p, dp]),
@@ -139,7 +144,8 @@ class Problem:
         self.c = _Problem(self.ndim, int(get("recon")), int(get("rk")), len(blocks),
                           self.ncell, float(get("gamma")), float(get("cfl")),
                           float(get("dx")), float(get("dy")), float(get("dz")),
-                          C.cast(self._blocks, C.c_void_p), C.cast(self._links, C.c_void_p))
+                          C.cast(self._blocks, C.c_void_p), C.cast(self._links, C.c_void_p),
+                          float(override.get("weno_eps", getattr(prob, "weno_eps", WENO_EPS))))
 
     @property
     def ptr(self):
@@ -285,12 +291,37 @@ def plm(q):
     return qm, qp, code
 
 
-def weno5(q):
+def weno5(q, eps=None):
     q = np.ascontiguousarray(q, dtype=np.float64)
     n = q.shape[0]
     qm, qp = np.zeros(n), np.zeros(n)
-    lib().ora_weno5_n(n, _dp(q), _dp(qm), _dp(qp))
+    lib().ora_weno5_n(n, _dp(q), WENO_EPS if eps is None else float(eps), _dp(qm), _dp(qp))
     return qm, qp
+
+
+def recon_cell(prob, w):
+    """Reconstruction of cells along a line with the positivity fallback:
+    w (n, 2R+1, 5) stencil primitives per cell (R = 1 PLM-MC, 2 WENO5) ->
+    (qm, qp) (n, 5) left/right face values and fb (n,) fallback flags."""
+    P = _as_problem(prob)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    n = w.shape[0]
+    qm, qp, fb = np.zeros((n, 5)), np.zeros((n, 5)), np.zeros(n, dtype=np.int32)
+    lib().ora_recon_cell_n(P.ptr, n, _dp(w), _dp(qm), _dp(qp), _ip(fb))
+    return qm, qp, fb
+
+
+def faces(prob, U, direction):
+    """Face values along a direction of every interior cell of a guard-filled
+    state U: (qm, qp) (5, ncell) primitives (NaN outside the interior) and
+    fb (ncell,) where the positivity fallback fired."""
+    P = _as_problem(prob)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    qm = np.full((5, P.ncell), np.nan)
+    qp = np.full((5, P.ncell), np.nan)
+    fb = np.zeros(P.ncell, dtype=np.int32)
+    _check(lib().ora_faces(P.ptr, _dp(U), int(direction), _dp(qm), _dp(qp), _ip(fb)), "faces")
+    return qm, qp, fb
 
 
 def hllc(prob, WL, WR, direction):
@@ -330,10 +361,11 @@ def plm_vjp(q, gqm, gqp):
     return gq
 
 
-def weno5_vjp(q, gqm, gqp):
+def weno5_vjp(q, gqm, gqp, eps=None):
     q = np.ascontiguousarray(q, dtype=np.float64)
     gq = np.zeros_like(q)
-    lib().ora_weno5_vjp_n(q.shape[0], _dp(q), _dp(np.ascontiguousarray(gqm, dtype=np.float64)),
+    lib().ora_weno5_vjp_n(q.shape[0], _dp(q), WENO_EPS if eps is None else float(eps),
+                          _dp(np.ascontiguousarray(gqm, dtype=np.float64)),
                           _dp(np.ascontiguousarray(gqp, dtype=np.float64)), _dp(gq))
     return gq
 
@@ -367,12 +399,13 @@ def plm_cs(q, v, h=1e-30):
     return (mr, mi / h), (pr, pi / h)
 
 
-def weno5_cs(q, v, h=1e-30):
+def weno5_cs(q, v, h=1e-30, eps=None):
     qr = np.ascontiguousarray(q, dtype=np.float64)
     qi = np.ascontiguousarray(v * h, dtype=np.float64)
     n = q.shape[0]
     mr, mi, pr, pi = (np.zeros(n) for _ in range(4))
-    lib().ora_cs_weno5_n(n, _dp(qr), _dp(qi), _dp(mr), _dp(mi), _dp(pr), _dp(pi))
+    lib().ora_cs_weno5_n(n, _dp(qr), _dp(qi), WENO_EPS if eps is None else float(eps),
+                         _dp(mr), _dp(mi), _dp(pr), _dp(pi))
     return (mr, mi / h), (pr, pi / h)
 
 

@@ -33,6 +33,7 @@ static int validate(const ora_problem *P)
     if (P->nblocks < 0 || P->ncell < 0) return ORA_EINVAL;
     if (!(P->gamma > 1.0) || !(P->cfl > 0.0) || !(P->dx > 0.0) || !(P->dy > 0.0) || !(P->dz > 0.0))
         return ORA_EINVAL;
+    if (!(P->weno_eps > 0.0) || !isfinite(P->weno_eps)) return ORA_EINVAL;
     int ngmin = (P->recon == 1) ? 3 : 2;
     /* extents, guard width, range of offsets */
     for (int b = 0; b < P->nblocks; b++) {
@@ -338,9 +339,9 @@ static void plm_vjp(int code, double gqm, double gqp, double *ga, double *g0, do
 }
 
 /* Reverse of WENO5-JS (both faces share the smoothness indicators). */
-static void weno5_vjp(const double *q, double gqm, double gqp, double *g)
+static void weno5_vjp(const double *q, double eps, double gqm, double gqp, double *g)
 {
-    const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
+    const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0;
     double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
     double t[3], w[3], be[3], s[3], o[3];
     t[0] = (a - 2.0 * b) + c;  w[0] = (a - 4.0 * b) + 3.0 * c;
@@ -573,19 +574,9 @@ static void block_rhs_vjp(const ora_problem *P, int b, const double *U, const do
                     for (int v = 0; v < nv; v++) Uln[5 * (t + 1 + R) + v] = U[v * nc + ci];
                     ora_r_eos(P, &Uln[5 * (t + 1 + R)], &W[5 * (t + 1 + R)]);
                 }
-                for (int t = -1; t <= n; t++) {
-                    const double *w0 = &W[5 * (t + 1 + R)];
-                    double *m = &qm[5 * (t + 1)], *p = &qp[5 * (t + 1)];
-                    for (int q = 0; q < 5; q++) {
-                        code[5 * (t + 1) + q] = 0;
-                        if (q == 3 && nd == 2) { m[q] = 0.0; p[q] = 0.0; continue; }
-                        if (R == 1) ora_r_plm(w0[q - 5], w0[q], w0[q + 5], &m[q], &p[q], &code[5 * (t + 1) + q]);
-                        else ora_r_weno5(w0[q - 10], w0[q - 5], w0[q], w0[q + 5], w0[q + 10], &m[q], &p[q]);
-                    }
-                    fb[t + 1] = !(m[0] > 0.0 && m[4] > 0.0) || !(p[0] > 0.0 && p[4] > 0.0);
-                    if (fb[t + 1])
-                        for (int q = 0; q < 5; q++) { m[q] = w0[q]; p[q] = w0[q]; }
-                }
+                for (int t = -1; t <= n; t++)
+                    fb[t + 1] = ora_r_recon_cell(P, &W[5 * (t + 1 + R)], &qm[5 * (t + 1)], &qp[5 * (t + 1)],
+                                                 &code[5 * (t + 1)]);
                 /* reverse: flux differences -> face flux cotangents */
                 for (int i = 0; i < 5 * (n + 1); i++) gF[i] = 0.0;
                 for (int t = 0; t < n; t++) {
@@ -626,7 +617,7 @@ static void block_rhs_vjp(const ora_problem *P, int b, const double *U, const do
                         } else {
                             double st[5], gs[5] = {0, 0, 0, 0, 0};
                             for (int k = 0; k < 5; k++) st[k] = W[5 * (c0 - 2 + k) + q];
-                            weno5_vjp(st, gm[q], gp[q], gs);
+                            weno5_vjp(st, P->weno_eps, gm[q], gp[q], gs);
                             for (int k = 0; k < 5; k++) gW[5 * (c0 - 2 + k) + q] += gs[k];
                         }
                     }
@@ -787,10 +778,67 @@ void ora_plm_n(int64_t n, const double *q, double *qm, double *qp, int *code)
     for (int64_t i = 0; i < n; i++) ora_r_plm(q[3 * i], q[3 * i + 1], q[3 * i + 2], &qm[i], &qp[i], &code[i]);
 }
 
-void ora_weno5_n(int64_t n, const double *q, double *qm, double *qp)
+void ora_weno5_n(int64_t n, const double *q, double eps, double *qm, double *qp)
 {
     for (int64_t i = 0; i < n; i++)
-        ora_r_weno5(q[5 * i], q[5 * i + 1], q[5 * i + 2], q[5 * i + 3], q[5 * i + 4], &qm[i], &qp[i]);
+        ora_r_weno5(q[5 * i], q[5 * i + 1], q[5 * i + 2], q[5 * i + 3], q[5 * i + 4], eps, &qm[i], &qp[i]);
+}
+
+/* Reconstruction of n cells along a line with the positivity fallback (the
+ * step's calcLims for one cell and direction): w holds, per cell, the
+ * primitives (rho, u_x, u_y, u_z, p) of its 2R+1 stencil cells (R = 1 PLM-MC,
+ * 2 WENO5), the cell itself in the middle; qm, qp receive its left- and
+ * right-face values (5 each), fb whether the fallback fired. */
+void ora_recon_cell_n(const ora_problem *P, int64_t n, const double *w, double *qm, double *qp, int *fb)
+{
+    const int R = (P->recon == 1) ? 2 : 1;
+    for (int64_t i = 0; i < n; i++)
+        fb[i] = ora_r_recon_cell(P, &w[5 * ((2 * R + 1) * i + R)], &qm[5 * i], &qp[5 * i], NULL);
+}
+
+/* Face values of every interior cell along direction d, from a state whose
+ * guard cells are filled (ora_fill_guards): qm, qp (5 x ncell, primitives,
+ * padded layout; entries outside the interior are left as they are) and fb
+ * (ncell; 1 where the positivity fallback fired, 0 elsewhere in the
+ * interior).  The same line walk as the stage: primitives from the EOS,
+ * then the reconstruction of each cell. */
+int ora_faces(const ora_problem *P, const double *U, int d, double *qm, double *qp, int *fb)
+{
+    int rc = validate(P);
+    if (rc) return rc;
+    if (d < 0 || d >= P->ndim) return ORA_EINVAL;
+    const int nd = P->ndim, nv = nd + 2, R = (P->recon == 1) ? 2 : 1;
+    const int64_t nc = P->ncell;
+    int64_t bad = 0;
+    for (int b = 0; b < P->nblocks; b++) {
+        const ora_block *B = &P->blocks[b];
+        int n = ora_r_extent(B, d);
+        int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
+        int n1 = ora_r_extent(B, o1), n2 = (nd == 3) ? ora_r_extent(B, o2) : 1;
+        double *W = malloc(sizeof(double) * 5 * (n + 2 * R));
+        for (int e2 = 0; e2 < n2; e2++)
+            for (int e1 = 0; e1 < n1; e1++) {
+                int pos[3];
+                for (int t = -R; t < n + R; t++) {
+                    pos[d] = t;  pos[o1] = e1;  pos[o2] = e2;
+                    if (nd == 2) pos[2] = 0;
+                    int64_t ci = ora_r_cell(B, nd, pos[0], pos[1], pos[2]);
+                    double Uc[5];
+                    for (int v = 0; v < nv; v++) Uc[v] = U[v * nc + ci];
+                    bad += ora_r_eos(P, Uc, &W[5 * (t + R)]);
+                }
+                for (int t = 0; t < n; t++) {
+                    pos[d] = t;  pos[o1] = e1;  pos[o2] = e2;
+                    if (nd == 2) pos[2] = 0;
+                    int64_t ci = ora_r_cell(B, nd, pos[0], pos[1], pos[2]);
+                    double m[5], p[5];
+                    fb[ci] = ora_r_recon_cell(P, &W[5 * (t + R)], m, p, NULL);
+                    for (int q = 0; q < 5; q++) { qm[q * nc + ci] = m[q]; qp[q * nc + ci] = p[q]; }
+                }
+            }
+        free(W);
+    }
+    return bad ? ORA_ENONPHYS : ORA_OK;
 }
 
 int ora_hllc_n(const ora_problem *P, int64_t n, int dir, const double *WL, const double *WR, double *F, int *tape)
@@ -831,11 +879,11 @@ void ora_plm_vjp_n(int64_t n, const double *q, const double *gqm, const double *
     }
 }
 
-void ora_weno5_vjp_n(int64_t n, const double *q, const double *gqm, const double *gqp, double *gq)
+void ora_weno5_vjp_n(int64_t n, const double *q, double eps, const double *gqm, const double *gqp, double *gq)
 {
     for (int64_t i = 0; i < n; i++) {
         for (int k = 0; k < 5; k++) gq[5 * i + k] = 0.0;
-        weno5_vjp(&q[5 * i], gqm[i], gqp[i], &gq[5 * i]);
+        weno5_vjp(&q[5 * i], eps, gqm[i], gqp[i], &gq[5 * i]);
     }
 }
 

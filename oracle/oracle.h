@@ -36,6 +36,7 @@ typedef struct {
     double gamma, cfl, dx, dy, dz;
     const ora_block *blocks;
     const ora_link *links;
+    double weno_eps;        /* epsilon of the WENO5 weights (Jiang & Shu: 1e-6) */
 } ora_problem;
 
 /* Two-level-ratio block AMR (refinement ratio 2, levels differ by at most

@@ -90,12 +90,13 @@ void ora_cs_plm_n(int64_t n, const double *qr, const double *qi, double *mr, dou
     }
 }
 
-void ora_cs_weno5_n(int64_t n, const double *qr, const double *qi, double *mr, double *mi, double *pr, double *pi)
+void ora_cs_weno5_n(int64_t n, const double *qr, const double *qi, double eps, double *mr, double *mi, double *pr,
+                    double *pi)
 {
     for (int64_t i = 0; i < n; i++) {
         cplx q[5], m, p;
         pack(5, &qr[5 * i], &qi[5 * i], q);
-        ora_c_weno5(q[0], q[1], q[2], q[3], q[4], &m, &p);
+        ora_c_weno5(q[0], q[1], q[2], q[3], q[4], eps, &m, &p);
         mr[i] = creal(m); mi[i] = cimag(m); pr[i] = creal(p); pi[i] = cimag(p);
     }
 }

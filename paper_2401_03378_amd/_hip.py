@@ -25,6 +25,8 @@ EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create
            "hydro_fp_check")
 FLAG_LEVEL_BY_LEVEL = 1
 HYDRO_DT_FROM_PREVIOUS = 2
+HYDRO_DT_RECORD = 3
+WENO_EPS = 1e-6          # Jiang & Shu's epsilon, the default of a problem without weno_eps
 
 
 class HydroError(RuntimeError):
@@ -49,7 +51,8 @@ class Amr(C.Structure):
 class Params(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("recon", C.c_int32), ("rk", C.c_int32),
                 ("flags", C.c_int32), ("gamma", C.c_double), ("cfl", C.c_double),
-                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("weno_eps", C.c_double)]
 
 
 class Tuning(C.Structure):
@@ -114,7 +117,8 @@ def tables(prob):
         for f in range(6):
             L[i].nbr[f] = int(links[i]["nbr"][f])
     P = Params(int(prob.ndim), int(prob.recon), int(prob.rk), 0, float(prob.gamma),
-               float(prob.cfl), float(prob.dx), float(prob.dy), float(prob.dz))
+               float(prob.cfl), float(prob.dx), float(prob.dy), float(prob.dz),
+               float(getattr(prob, "weno_eps", WENO_EPS)))
     return P, B, L, nb
 
 

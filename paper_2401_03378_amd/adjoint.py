@@ -55,8 +55,11 @@ def rollout(stepper, U0, nsteps, k, dts=None, keep_last=False):
             # out of place from here on: U itself is the checkpoint
             if n == last:
                 tape.checkpoints[n] = U
-            # the returned state takes its guard cells from U0, as in place
-            Unext, aux, dt = keep(U, dtn, stepper.copy(U) if n == nsteps - 1 else None)
+            # the returned state takes its guard cells from U0, as in place:
+            # the segment's checkpoint holds them (it was stepped in place;
+            # the states step_keep returns in between have unspecified guards)
+            out = stepper.copy(tape.checkpoints[last]) if n == nsteps - 1 else None
+            Unext, aux, dt = keep(U, dtn, out)
             tape.tail[n] = (U, aux)
             U = Unext
         else:
@@ -126,7 +129,9 @@ class TorchStepper:
 
     def step(self, U, dt=None):
         # a rollout steps one state in place: its CFL dt can come from the
-        # maxima the previous step recorded (the same dt, bit for bit)
+        # maxima the previous step recorded (the same dt, bit for bit); the
+        # solver allows that only for the tensor that step wrote, so the first
+        # step of a rollout (a fresh copy of U0) computes its dt from U
         d = self.S.step(U, dt, dt_from_previous=dt is None)
         return float(d.item()) if torch.is_tensor(d) else float(d)
 

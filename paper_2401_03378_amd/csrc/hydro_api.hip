@@ -128,6 +128,7 @@ std::string check_problem(const hydro_params_t *p, const hydro_block_t *blocks, 
     if (p->rk != 2 && p->rk != 3) return "rk must be 2 or 3";
     if (!(p->gamma > 1.0)) return "gamma must be > 1";
     if (!(p->cfl > 0.0) || !(p->dx > 0.0) || !(p->dy > 0.0) || !(p->dz > 0.0)) return "cfl and cell widths must be > 0";
+    if (!(p->weno_eps > 0.0) || !std::isfinite(p->weno_eps)) return "weno_eps must be finite and > 0";
     const int ngmin = (p->recon == HYDRO_WENO5) ? 3 : 2;
     std::vector<std::pair<int64_t, int64_t>> span(nblocks);
     for (int b = 0; b < nblocks; ++b) {
@@ -448,6 +449,7 @@ StageArgs stage_args(hydro_ctx *c, int s, const double *dt, const double *Un, co
     a.idy = 1.0 / c->prm.dy;
     a.idz = 1.0 / c->prm.dz;
     rk_coeffs(c->prm.rk, s, a.a, a.b);
+    a.eps = c->prm.weno_eps;
     a.dt = dt;
     a.Un = Un;
     a.Us = Us;
@@ -1219,8 +1221,9 @@ int hydro_step(hydro_ctx_t *c, double *U, double *dt_dev, int32_t compute_dt)
     // dt mode (see enqueue_step): fused only in the persistent form on a mesh
     // without levels, where the final stage covers every cell in one launch
     int cdt = compute_dt ? 1 : 0;
-    if (compute_dt == HYDRO_DT_FROM_PREVIOUS && c->tune.mode == HYDRO_MODE_PERSISTENT && !c->amr)
-        cdt = (c->cfl_next_U == U) ? 2 : 3;
+    if ((compute_dt == HYDRO_DT_FROM_PREVIOUS || compute_dt == HYDRO_DT_RECORD) &&
+        c->tune.mode == HYDRO_MODE_PERSISTENT && !c->amr)
+        cdt = (compute_dt == HYDRO_DT_FROM_PREVIOUS && c->cfl_next_U == U) ? 2 : 3;
     // the recorded maxima describe U only once this step is enqueued
     c->cfl_next_U = nullptr;
     const int rc = step_launch(c, U, dt_dev, cdt);
@@ -1236,6 +1239,7 @@ static int step_vjp(hydro_ctx_t *c, const double *Un, const double *const *stage
 {
     if (!c || !Un || !dt_dev || !gUnext || !gUn) return fail(c, HYDRO_EINVAL, "null pointer");
     if (gUn == gUnext) return fail(c, HYDRO_EINVAL, "gUn aliases gUnext");
+    if (gUn == Un) return fail(c, HYDRO_EINVAL, "gUn aliases Un");
     if (c->tune.mode == HYDRO_MODE_TELESCOPING)
         return fail(c, HYDRO_EINVAL, "the adjoint is defined for the per-stage-fill step only");
     if (c->amr) return fail(c, HYDRO_EINVAL, "the adjoint is defined on meshes without refinement levels");
@@ -1281,6 +1285,7 @@ static int step_vjp(hydro_ctx_t *c, const double *Un, const double *const *stage
         v.idy = 1.0 / c->prm.dy;
         v.idz = 1.0 / c->prm.dz;
         rk_coeffs(S, s, v.a, v.b);
+        v.eps = c->prm.weno_eps;
         v.dt = dt_dev;
         v.Us = Us_of[s];
         v.gOut = g;

@@ -132,12 +132,14 @@ __device__ __forceinline__ void plm(double qa, double q0, double qb, double &qm,
 
 // WENO5-JS on (a,b,c,d,e) = q_{i-2..i+2}; both faces share beta_k.
 // Candidates and indicators are evaluated with fused multiply-adds in the
-// order written; the weights are alpha_k = d_k / s_k, s_k = (eps + beta_k)^2,
+// order written; the weights are alpha_k = d_k / s_k, s_k = (eps + beta_k)^2
+// (eps: the problem's weno_eps, 1e-6 in Jiang & Shu),
 // scaled by s_0 s_1 s_2 (the normalised weights are unchanged), so the only
 // divisions are one per face.
-__device__ __forceinline__ void weno5(double a, double b, double c, double d, double e, double &qm, double &qp)
+__device__ __forceinline__ void weno5(double a, double b, double c, double d, double e, double eps, double &qm,
+                                      double &qp)
 {
-    const double k13 = 13.0 / 12.0, eps = 1e-6;
+    const double k13 = 13.0 / 12.0;
     const double c13 = 1.0 / 3.0, c16 = 1.0 / 6.0, c56 = 5.0 / 6.0, c76 = 7.0 / 6.0, c116 = 11.0 / 6.0;
     double t, w;
     t = fma(-2.0, b, a) + c;
@@ -172,16 +174,16 @@ __device__ __forceinline__ void weno5(double a, double b, double c, double d, do
 // Reconstruct all primitives of one cell along a line; s[c][v] is the
 // stencil (2R+1 cells).  Applies the positivity fallback (both faces become
 // the cell value when either face has non-positive density or pressure).
-// Returns true if the fallback fired.
+// Returns true if the fallback fired.  eps: the WENO5 weight epsilon.
 template <int NDIM, int RECON, int S>
-__device__ __forceinline__ bool recon_cell(const double (&s)[S][5], double (&qm)[5], double (&qp)[5])
+__device__ __forceinline__ bool recon_cell(const double (&s)[S][5], double (&qm)[5], double (&qp)[5], double eps)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
         if (NDIM == 2 && v == 3) { qm[v] = 0.0; qp[v] = 0.0; continue; }
         if constexpr (RECON == kWENO)
-            weno5(s[R - 2][v], s[R - 1][v], s[R][v], s[R + 1][v], s[R + 2][v], qm[v], qp[v]);
+            weno5(s[R - 2][v], s[R - 1][v], s[R][v], s[R + 1][v], s[R + 2][v], eps, qm[v], qp[v]);
         else
             plm(s[R - 1][v], s[R][v], s[R + 1][v], qm[v], qp[v]);
     }

@@ -149,8 +149,8 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) { s0[c][v] = Wt[c][v]; s1[c][v] = Wt[c + 1][v]; }
                 double qa[5], qb[5], qm[5];
-                recon_cell<NDIM, RECON>(s0, qa, qpz);      // cell z0-1: keep its right face
-                recon_cell<NDIM, RECON>(s1, qm, qb);       // cell z0
+                recon_cell<NDIM, RECON>(s0, qa, qpz, A.eps);      // cell z0-1: keep its right face
+                recon_cell<NDIM, RECON>(s1, qm, qb, A.eps);       // cell z0
                 bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Flo, K);
                 if (z0 == 0) reg_put(4, i, j, Flo);
 #pragma unroll
@@ -194,7 +194,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = zw[R - 1][v];
                     double qm[5], qp[5], Fhi[5];
-                    recon_cell<NDIM, RECON>(zw, qm, qp);   // cell k+1
+                    recon_cell<NDIM, RECON>(zw, qm, qp, A.eps);   // cell k+1
                     bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Fhi, K);
                     if (k == B.nz - 1) reg_put(5, i, j, Fhi);
 #pragma unroll
@@ -266,14 +266,14 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 for (int c = 0; c < NW; ++c)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) s[c][v] = sW[v][ty + H][tx + H - R + c];
-                recon_cell<NDIM, RECON>(s, qmx, qp);
+                recon_cell<NDIM, RECON>(s, qmx, qp, A.eps);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sQx[v][ty][tx + 1] = qp[v];
 #pragma unroll
                 for (int c = 0; c < NW; ++c)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) s[c][v] = sW[v][ty + H - R + c][tx + H];
-                recon_cell<NDIM, RECON>(s, qmy, qp);
+                recon_cell<NDIM, RECON>(s, qmy, qp, A.eps);
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sQy[v][ty + 1][tx] = qp[v];
             }
@@ -299,7 +299,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
 #pragma unroll
                         for (int v = 0; v < 5; ++v) s[c][v] = sW[v][cy + H - R + c][epos + H];
                 }
-                recon_cell<NDIM, RECON>(s, qm, qp);
+                recon_cell<NDIM, RECON>(s, qm, qp, A.eps);
                 if (etype == 0) {
 #pragma unroll
                     for (int v = 0; v < 5; ++v) sQx[v][epos][0] = qp[v];

@@ -14,6 +14,7 @@ struct StageArgs {
     double gamma, g1, ig1;
     double idx, idy, idz;
     double a, b;                // U_out = b T + a U^n for stage >= 2
+    double eps;                 // WENO5 weight epsilon
     const double *dt;           // device scalar
     const double *Un;
     const double *Us;
@@ -83,6 +84,7 @@ struct VjpArgs {
     double gamma, g1, ig1;
     double idx, idy, idz;
     double a, b;
+    double eps;                 // WENO5 weight epsilon
     const double *dt;
     const double *Us;           // stage input (forward state)
     const double *gOut;         // cotangent of the stage output (interior)

@@ -242,12 +242,12 @@ __device__ __forceinline__ void plm_vjp(double qa, double q0, double qb, double 
 }
 
 // Reverse of WENO5-JS on (a,b,c,d,e): adds to g[0..4].
-__device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gqp, double *g)
+__device__ __forceinline__ void weno5_vjp(const double *q, double eps, double gqm, double gqp, double *g)
 {
     // Forward: s_k = (eps + beta_k)^2, o_k = product of the two other s_j,
     // face value = sum(d_k o_k p_k) / sum(d_k o_k).  One reciprocal per face
     // (the face value is recomputed here for its derivatives only).
-    const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0, eps = 1e-6;
+    const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0;
     const double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
     double t[3], w[3], sq[3], s[3];
     t[0] = (a - 2.0 * b) + c;
@@ -319,7 +319,7 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double gqm, double gq
 // (2R+1 cells); fb: the positivity fallback fired (faces = cell value).
 template <int NDIM, int RECON, int S>
 __device__ __forceinline__ void recon_cell_vjp(const double (&s)[S][5], bool fb, const double (&gqm)[5],
-                                               const double (&gqp)[5], double (&g)[S][5])
+                                               const double (&gqp)[5], double (&g)[S][5], double eps)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
     if (fb) {
@@ -334,7 +334,7 @@ __device__ __forceinline__ void recon_cell_vjp(const double (&s)[S][5], bool fb,
 #pragma unroll
         for (int k = 0; k < 2 * R + 1; ++k) { st[k] = s[k][v]; gs[k] = 0.0; }
         if constexpr (RECON == kWENO)
-            weno5_vjp(st, gqm[v], gqp[v], gs);
+            weno5_vjp(st, eps, gqm[v], gqp[v], gs);
         else
             plm_vjp(st[0], st[1], st[2], gqm[v], gqp[v], gs);
 #pragma unroll
@@ -474,7 +474,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
             for (int q = 0; q < NS; ++q)
 #pragma unroll
                 for (int v = 0; v < 5; ++v) s[q][v] = Wwin[q + 1][v];
-            const bool fb = recon_cell<NDIM, RECON>(s, qm, qp);
+            const bool fb = recon_cell<NDIM, RECON>(s, qm, qp, A.eps);
             double gqp_c1[5] = {0, 0, 0, 0, 0}, gqm_c[5] = {0, 0, 0, 0, 0};
             if (c >= f0) {
                 // cotangent of face c-1/2: gD_{c-1} - gD_c
@@ -502,7 +502,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
                 for (int q = 0; q < NS; ++q)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) { s1[q][v] = Wwin[q][v]; g1[q][v] = 0.0; }
-                recon_cell_vjp<NDIM, RECON>(s1, fb_prev, gqm_prev, gqp_c1, g1);
+                recon_cell_vjp<NDIM, RECON>(s1, fb_prev, gqm_prev, gqp_c1, g1, A.eps);
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
 #pragma unroll
@@ -530,7 +530,7 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
         for (int q = 0; q < NS; ++q)
 #pragma unroll
             for (int v = 0; v < 5; ++v) { s1[q][v] = Wwin[q + 1][v]; g1[q][v] = 0.0; }
-        recon_cell_vjp<NDIM, RECON>(s1, fb_prev, gqm_prev, zero, g1);
+        recon_cell_vjp<NDIM, RECON>(s1, fb_prev, gqm_prev, zero, g1, A.eps);
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
 #pragma unroll

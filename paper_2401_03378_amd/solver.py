@@ -3,6 +3,7 @@ every computation in libhydro's HIP kernels (through the C ABI)."""
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 
 import numpy as np
 import torch
@@ -14,6 +15,34 @@ from ._hip import HydroError, Tuning
 def _ptr(t):
     assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
     return C.c_void_p(t.data_ptr())
+
+
+class CflRecord:
+    """Whether a step of U may take its CFL dt from the maxima the previous
+    step recorded (HYDRO_DT_FROM_PREVIOUS).  Only when U is the very tensor
+    the previous such step wrote: still alive (so its memory cannot have been
+    freed and handed to another tensor at the same address) and not written
+    through torch since (its version counter is unchanged; the library's own
+    writes do not count).  Otherwise the step computes the CFL dt from U and
+    records the maxima of the state it writes (HYDRO_DT_RECORD)."""
+
+    def __init__(self):
+        self._ref = None
+        self._ver = None
+
+    def mode(self, U):
+        last = self._ref() if self._ref is not None else None
+        if last is U and U._version == self._ver:
+            return _hip.HYDRO_DT_FROM_PREVIOUS
+        return _hip.HYDRO_DT_RECORD
+
+    def wrote(self, U):
+        self._ref = weakref.ref(U)
+        self._ver = U._version
+
+    def forget(self):
+        self._ref = None
+        self._ver = None
 
 
 class Solver:
@@ -47,6 +76,7 @@ class Solver:
             raise HydroError(rc, self._L.hydro_last_error(None).decode())
         self.ctx = ctx
         self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._cfl = CflRecord()
         if tuning:
             self.set_tuning(**tuning)
 
@@ -78,6 +108,7 @@ class Solver:
         cur = self.tuning()
         cur.update(kw)
         t = Tuning(**cur)
+        self._cfl.forget()
         self._check(self._L.hydro_set_tuning(self.ctx, C.byref(t)))
 
     # ------------------------------------------------------------ the method
@@ -91,18 +122,23 @@ class Solver:
 
     def rk_stage(self, stage, Un, Us, Uout, dt=None):
         dt = self.dt if dt is None else dt
+        self._cfl.forget()
         self._check(self._L.hydro_rk_stage(self.ctx, int(stage), _ptr(dt), _ptr(Un), _ptr(Us), _ptr(Uout)))
 
     def step(self, U, dt=None, dt_from_previous=False):
         """One step in place.  dt None: CFL dt (left in self.dt); a float or a
         device tensor: that dt.  dt_from_previous (with dt None): the same dt,
-        taken from the maxima the previous such step recorded for U when U is
-        the state it wrote and nothing else has written it since
-        (HYDRO_DT_FROM_PREVIOUS)."""
+        taken from the maxima the previous such step recorded when U is the
+        tensor it wrote and nothing has written it since (CflRecord); else
+        computed from U and recorded for the next step."""
         if dt is None:
-            mode = _hip.HYDRO_DT_FROM_PREVIOUS if dt_from_previous else 1
+            mode = self._cfl.mode(U) if dt_from_previous else 1
+            self._cfl.forget()
             self._check(self._L.hydro_step(self.ctx, _ptr(U), _ptr(self.dt), mode))
+            if dt_from_previous:
+                self._cfl.wrote(U)
             return self.dt
+        self._cfl.forget()
         if not torch.is_tensor(dt):
             self.dt.fill_(float(dt))
             dt = self.dt
@@ -126,15 +162,19 @@ class Solver:
     def step_keep(self, Un, dt, out=None):
         """One step at dt out of place, stage by stage (hydro_rk_stage):
         returns (U^{n+1}, [U_2 .. U_S]), the stage inputs as step_vjp takes
-        them.  Un is not changed.  U^{n+1} is written into the interior of
-        out if given (its guard cells are left as they are), else into a new
-        tensor whose guard cells are unspecified, as are the stage inputs'."""
+        them.  Un is not changed (in the per-block and materialised modes,
+        whose stages write the guard cells of their input, the first stage
+        reads a copy of it).  U^{n+1} is written into the interior of out if
+        given (its guard cells are left as they are), else into a new tensor
+        whose guard cells are unspecified, as are the stage inputs'."""
         if out is not None and out.data_ptr() == Un.data_ptr():
             raise ValueError("out must not alias Un (step_keep leaves Un as it is)")
         d = self._dt_tensor(dt)
         S = int(self.prob.rk)
         stages = []
         Us = Un
+        if self.tuning()["mode"] in (_hip.MODE_PERBLOCK, _hip.MODE_MATERIALISED):
+            Us = Un.clone()
         for s in range(1, S):
             buf = torch.empty_like(Un)
             self.rk_stage(s, Un, Us, buf, d)

@@ -64,6 +64,7 @@ class Problem:
     grid: Optional[tuple] = None   # (NBx, NBy, NBz, n) for uniform block grids
     amr: Optional[np.ndarray] = None   # AMR_DTYPE per block, for meshes with refinement levels
     origin: Optional[np.ndarray] = None   # (nblocks, 3) lower corner of each block (AMR meshes)
+    weno_eps: float = 1e-6   # epsilon of the WENO5 nonlinear weights (Jiang & Shu 1996)
 
     @property
     def nvar(self) -> int:

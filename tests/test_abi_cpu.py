@@ -57,6 +57,10 @@ def _mut(f):
     lambda p: setattr(p, "rk", 4),
     lambda p: setattr(p, "recon", 2),
     lambda p: setattr(p, "ndim", 1),
+    lambda p: setattr(p, "weno_eps", 0.0),
+    lambda p: setattr(p, "weno_eps", -1e-6),
+    lambda p: setattr(p, "weno_eps", float("nan")),
+    lambda p: setattr(p, "weno_eps", float("inf")),
 ])
 def test_validate_rejects(f):
     assert _mut(f) == _hip.HYDRO_EINVAL

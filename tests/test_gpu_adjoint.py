@@ -203,25 +203,42 @@ def test_step_autograd_function_and_central_differences():
     m1 = torch.as_tensor(W.interior_mask(p.blocks, p.ncell, 2), device=U0.device)
     assert torch.equal(y1.detach()[:, m1], U1[:, m1])
     assert torch.equal(x1.grad, S.step_vjp(U0, torch.nan_to_num(w), dt))
-    good = 0
+    def grad_at(U):
+        # the gradient of <w, step(step(U))> at U, through the two step VJPs
+        U1 = U.clone()
+        S.step(U1, dt)
+        return S.step_vjp(U, S.step_vjp(U1, torch.nan_to_num(w), dt), dt)
+
+    g0 = grad_at(U0)
+    assert torch.equal(g0, grad)
+    scale = float(g0.abs().max())
+    accepted, rejected = 0, []
     for trial in range(30):
         v = S.to_device(np.where(m, rng.standard_normal(p.U0.shape), 0.0))
         h = 1e-7 * float(torch.nan_to_num(U0).abs().max()) / float(v.abs().max())
         up, um = U0 + h * v, U0 - h * v
+        # kink check: a direction whose perturbation crosses a branch (a
+        # limiter case, the fallback, an HLLC region or a Davis argument)
+        # changes the adjoint by O(1) somewhere; without a crossing it moves
+        # by O(h).  Such directions are left out, and counted.
+        dev = max(float((grad_at(up) - g0).abs().max()), float((grad_at(um) - g0).abs().max())) / scale
+        if dev > 1e-5:
+            rejected.append(dev)
+            continue
         for U in (up, um):
             S.step(U, dt)
             S.step(U, dt)
         fd = float(torch.nansum(w * (up - um))) / (2 * h)
         ad = float(torch.nansum(grad * v))
-        # reject directions whose perturbation crosses a branch: compare
-        # the adjoint at the perturbed states
-        rel = abs(fd - ad) / max(abs(fd), abs(ad))
-        if rel < 1e-6:
-            good += 1
-        if good >= 8:
+        # every direction that crosses no branch must agree
+        assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (trial, fd, ad)
+        accepted += 1
+        if accepted >= 8:
             break
     S.close()
-    assert good >= 8
+    print(f"central differences: {accepted} directions agree; {len(rejected)} crossed a branch "
+          f"(adjoint moved by {rejected} of its maximum)")
+    assert accepted >= 8
 
 
 @pytest.mark.parametrize("k", range(8))
@@ -248,7 +265,9 @@ def _kept_vs_recomputed(p, S, seed):
     m = torch.as_tensor(W.interior_mask(p.blocks, p.ncell, p.ndim), device=Ug.device)
     UN, stages = S.step_keep(Ug, dt)
     assert len(stages) == p.rk - 1
-    assert torch.equal(torch.nan_to_num(Ug), torch.nan_to_num(U_before))     # input left as it was
+    # input left as it was, guard cells included (NaN stays NaN)
+    assert torch.equal(Ug.isnan(), U_before.isnan())
+    assert torch.equal(torch.nan_to_num(Ug), torch.nan_to_num(U_before))
     Ustep = Ug.clone()
     S.step(Ustep, dt)
     assert torch.equal(UN[:, m], Ustep[:, m])                                # the same step, bit for bit
@@ -267,11 +286,14 @@ def _kept_vs_recomputed(p, S, seed):
 
 
 @pytest.mark.parametrize("ndim,recon,rk,n,ng,bc,NB", [SMALL[i] for i in (0, 2, 5, 6, 9)])
-def test_step_vjp_with_kept_stage_inputs(ndim, recon, rk, n, ng, bc, NB):
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_step_vjp_with_kept_stage_inputs(ndim, recon, rk, n, ng, bc, NB, mode):
     """hydro_step_vjp_stages fed the stage inputs of step_keep (hydro_rk_stage
-    stage by stage) gives hydro_step_vjp's result bit for bit."""
+    stage by stage) gives hydro_step_vjp's result bit for bit, and step_keep
+    leaves its input as it was, also in the per-block and materialised modes
+    whose stages write the guard cells of their input."""
     p = W.random_blocks(ndim, n, ng, seed=5, recon=recon, rk=rk, bc=bc, NB=NB)
-    S = _solver(p)
+    S = _solver(p, mode=mode)
     _kept_vs_recomputed(p, S, 12)
     S.close()
 
@@ -302,3 +324,64 @@ def test_rollout_gradient_in_materialising_modes(mode):
     assert out[0][0] == out[1][0]
     assert torch.equal(out[0][1], out[1][1])
     assert torch.equal(out[0][2], out[1][2])
+
+
+@pytest.mark.timeout(1200)
+def test_turbulence_rollout_gradient_128():
+    """The turbulence workload's adjoint rollout (10 steps, checkpoint every
+    5, seeded N(0,1) cotangent on all fields) at 128^3 from the same
+    generator: the 256^3 oracle adjoint would take the host tens of minutes."""
+    p = W.turb3d(N=128, n=16, seed=0)
+    w = _rand_cot(p, 6)
+    ost = OracleStepper(p)
+    _, tape_o = rollout(ost, p.U0, 10, 5)
+    g_o = rollout_vjp(ost, tape_o, w)
+    S = _solver(p)
+    st = TorchStepper(S)
+    UN, tape_g = rollout(st, S.to_device(p.U0), 10, 5, keep_last=True)
+    assert tape_g.dts == tape_o.dts
+    g_g = rollout_vjp(st, tape_g, S.to_device(w)).cpu().numpy()
+    S.status()
+    errs = assert_parity(p, g_g, g_o, "turb 128^3 rollout gradient")
+    print("turb 128^3 rollout gradient field errors", errs)
+    S.close()
+
+
+def test_second_rollout_after_freeing_the_first_state():
+    """A rollout whose final state is freed, then a fresh rollout from a new
+    copy of U0 (which the caching allocator may place at the same address):
+    the new rollout's first dt comes from its own state, so both runs give
+    the same dts and the same final state."""
+    p = W.random_blocks(3, 8, 3, seed=14, recon=1, rk=3, NB=(2, 2, 2))
+    S = _solver(p)
+    st = TorchStepper(S)
+    U0 = S.to_device(p.U0)
+    UN, tape = rollout(st, U0, 6, 3)
+    dts1, addr = list(tape.dts), UN.data_ptr()
+    m = torch.as_tensor(W.interior_mask(p.blocks, p.ncell, 3), device=U0.device)
+    first = UN[:, m].clone()
+    del UN, tape
+    UN2, tape2 = rollout(st, U0, 6, 3)
+    print("second rollout's state at the first one's address:", UN2.data_ptr() == addr)
+    assert tape2.dts == dts1
+    assert torch.equal(UN2[:, m], first)
+    dto = []
+    V = p.U0.copy()
+    for _ in range(6):
+        dto.append(O.step(p, V))
+    assert dts1 == dto
+    S.close()
+
+
+def test_step_vjp_rejects_gUn_aliasing_Un():
+    from paper_2401_03378_amd._hip import HydroError
+    p = W.random_blocks(2, 12, 2, seed=2, NB=(2, 2, 1))
+    S = _solver(p)
+    U = S.to_device(p.U0)
+    before = U.clone()
+    g = S.to_device(_rand_cot(p, 3))
+    with pytest.raises(HydroError):
+        S.step_vjp(U, g, 1e-3, gUn=U)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(U), torch.nan_to_num(before))
+    S.close()

@@ -118,12 +118,16 @@ def test_sedov_full_config():
     print("sedov3d field errors", errs)
 
 
-def test_batched_full_size_two_steps():
+@pytest.mark.timeout(900)
+def test_batched_full_size_all_steps():
+    """The batched workload at full size (4096 uneven blocks, 21.2 M zones)
+    over all 10 of its steps, in the default and the tuned launch."""
     p = W.config(2)
-    Uo, dto = _ora_run(p, 2)
-    Ug, dtg = _gpu_runs(p, 2)
+    Uo, dto = _ora_run(p, p.nsteps)
+    Ug, dtg = _gpu_runs(p, p.nsteps)
     np.testing.assert_array_equal(dtg, dto)
-    assert_parity(p, Ug, Uo, "batched", bitwise=True)
+    errs = assert_parity(p, Ug, Uo, "batched", bitwise=True)
+    print("batched field errors", errs)
 
 
 def test_batched_subset_all_steps():
@@ -142,12 +146,32 @@ def test_kh_full_config():
     assert_parity(p, Ug, Uo, "kh2d", bitwise=True)
 
 
-def test_turbulence_full_size_one_step():
+@pytest.mark.timeout(1200)
+def test_turbulence_full_size_all_steps():
+    """The 256^3 turbulence workload (4096 blocks of 16^3) over all 20 of
+    its steps, in the default and the tuned launch."""
     p = W.config(4)
-    Uo, dto = _ora_run(p, 1)
-    Ug, dtg = _gpu_runs(p, 1)
+    Uo, dto = _ora_run(p, p.nsteps)
+    Ug, dtg = _gpu_runs(p, p.nsteps)
     np.testing.assert_array_equal(dtg, dto)
-    assert_parity(p, Ug, Uo, "turb3d", bitwise=True)
+    errs = assert_parity(p, Ug, Uo, "turb3d", bitwise=True)
+    print("turb3d field errors", errs)
+
+
+def test_weno_epsilon_other_than_the_default():
+    """A problem's own WENO5 epsilon reaches the kernels: at eps = 1e-2 the
+    GPU steps equal the oracle's at that epsilon bit for bit, and differ from
+    the default epsilon's."""
+    p = W.random_blocks(3, 10, 3, seed=21, recon=W.WENO5, rk=3, bc="outflow")
+    q = p.copy()
+    q.weno_eps = 1e-2
+    Uo, dto = _ora_run(q, 3)
+    Ug, dtg = _gpu_run(q, 3)
+    np.testing.assert_array_equal(dtg, dto)
+    assert_parity(q, Ug, Uo, "weno eps 1e-2", bitwise=True)
+    Ud, _ = _gpu_run(p, 3)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    assert not np.array_equal(Ud[:, m], Ug[:, m])
 
 
 def test_turbulence_small_all_steps():

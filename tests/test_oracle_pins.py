@@ -176,6 +176,35 @@ def test_weno5_matches_normalised_weight_form():
     assert np.max(np.abs(qm - (wl * left).sum(axis=0)) / scale) < 1e-13
 
 
+def test_weno5_epsilon():
+    """The problem's epsilon enters the weights: far above every smoothness
+    indicator (eps = 1e20 for data of size <= 1e3) the weights are the linear
+    ones, so the faces are the fifth-order linear interpolants
+    (2a - 13b + 47c + 27d - 3e)/60 and its mirror even across jumps, where
+    the default epsilon picks the smooth side instead."""
+    rng = np.random.default_rng(12)
+    q = np.concatenate([rng.standard_normal((200, 5)) * 10.0 ** rng.uniform(-3, 3, (200, 1)),
+                        np.where(rng.random((200, 5)) < 0.5, 1.0, 0.0) * 100.0])
+    a, b, c, d, e = q.T
+    lin_p = (2 * a - 13 * b + 47 * c + 27 * d - 3 * e) / 60
+    lin_m = (2 * e - 13 * d + 47 * c + 27 * b - 3 * a) / 60
+    qm, qp = O.weno5(q, eps=1e20)
+    scale = np.maximum(np.max(np.abs(q), axis=1), 1.0)
+    assert np.max(np.abs(qp - lin_p) / scale) < 1e-13
+    assert np.max(np.abs(qm - lin_m) / scale) < 1e-13
+    jm, jp = O.weno5(np.array([[1.0, 1.0, 1.0, 0.0, 0.0]]))
+    assert abs(jp[0] - 1.0) < 1e-4 and abs(jp[0] - (2 - 13 + 47) / 60) > 0.1
+    # a step with another epsilon gives another state; bad values are rejected
+    p = W.random_blocks(3, 6, 3, seed=4, recon=W.WENO5, rk=3)
+    U1, U2 = p.U0.copy(), p.U0.copy()
+    O.step(p, U1, 1e-3)
+    O.step(O.Problem(p, weno_eps=1e-2), U2, 1e-3)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    assert not np.array_equal(U1[:, m], U2[:, m])
+    for bad in (0.0, -1e-6, float("nan"), float("inf")):
+        assert O.validate(O.Problem(p, weno_eps=bad)) == O.ORA_EINVAL
+
+
 def test_weno5_step_is_essentially_non_oscillatory():
     q = np.array([[1.0, 1.0, 1.0, 0.0, 0.0], [1.0, 1.0, 0.0, 0.0, 0.0]])
     qm, qp = O.weno5(q)
@@ -503,3 +532,47 @@ def test_sedov_symmetry_and_radius():
     R_ex = A.sedov_radius(1.0, t, 1.0, gold["xi0"])
     assert abs(R_num - R_ex) / R_ex < 0.1, (R_num, R_ex, steps)
     assert 2.0 < rho.max() < 6.0       # compression below the strong-shock limit
+
+
+def _sedov_to_radius(N, R):
+    """Oracle run of the Sedov problem (E = 1 in 3.5 cells, rho0 = 1) on N^3
+    cells up to the time the similarity solution puts the shock at R (the
+    last dt shortened to land on it)."""
+    gold = json.load(open(os.path.join(GOLD, "sedov_constant.json")))
+    tend = (R / gold["xi0"]) ** 2.5
+    p = W.sedov3d(N=N, n=16, radius_cells=3.5)
+    U = p.U0.copy()
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    E0 = math.fsum(U[4, m])
+    t = 0.0
+    while t < tend:
+        dt = min(O.cfl_dt(p, U), tend - t)
+        O.step(p, U, dt)
+        t += dt
+    G = W.gather_global(U, p.blocks, p.grid, 3)
+    xc = (np.arange(N) + 0.5) / N - 0.5
+    rr = np.sqrt(xc[:, None, None] ** 2 + xc[None, :, None] ** 2 + xc[None, None, :] ** 2)
+    rho = G[0]
+    shell = rho > 1.0 + 0.5 * (rho.max() - 1.0)
+    R_num = np.sum(rr * rho * shell) / np.sum(rho * shell)
+    return R_num, A.sedov_radius(1.0, t, 1.0, gold["xi0"]), rho, math.fsum(U[4, m]) / E0
+
+
+@pytest.mark.slow
+def test_sedov_radius_and_compression_under_refinement():
+    """Sedov at 64^3 run to R = 0.25 (about 220 steps): the shock radius
+    (density-weighted mean radius of the shell above half the peak) lies
+    within 5% of the similarity radius xi0 (E t^2/rho0)^(1/5) (Taylor 1950;
+    xi0 from Kamm & Timmes 2007), and the peak density rises from the 32^3
+    run toward the strong-shock limit (gamma+1)/(gamma-1) = 6 without
+    reaching it; energy is conserved while the blast is inside the domain;
+    the 64^3 blast keeps its octant mirror symmetry."""
+    R32, Rex32, rho32, e32 = _sedov_to_radius(32, 0.25)
+    R64, Rex64, rho64, e64 = _sedov_to_radius(64, 0.25)
+    assert abs(R64 - Rex64) / Rex64 < 0.05, (R64, Rex64)
+    assert abs(R64 - Rex64) <= abs(R32 - Rex32)
+    assert rho32.max() < rho64.max() < 6.0, (rho32.max(), rho64.max())
+    assert abs(e32 - 1.0) <= 1e-12 and abs(e64 - 1.0) <= 1e-12
+    s = rho64.max()
+    assert np.max(np.abs(rho64 - rho64[::-1, :, :])) <= 1e-12 * s
+    assert np.max(np.abs(rho64 - rho64.transpose(2, 1, 0))) <= 1e-12 * s

@@ -51,19 +51,22 @@ def test_rollout_gradient_matches_complex_step():
 
 class _KeepingStepper(OracleStepper):
     """A stepper whose step_keep hands back what it was given, so that the
-    rollout's pairing of kept data with steps can be checked."""
+    rollout's pairing of kept data with steps can be checked.  Like the GPU
+    solver's step_keep it writes the interior only: a fresh output's guard
+    cells hold arbitrary values (here random ones), out's stay as they were."""
 
     def __init__(self, prob):
         super().__init__(prob)
         self.used = 0
+        self.m = W.interior_mask(prob.blocks, prob.ncell, prob.ndim)
+        self.rng = np.random.default_rng(99)
 
     def step_keep(self, Un, dt=None, out=None):
         U = Un.copy()
         dt = O.step(self.p, U, dt)
-        if out is not None:
-            out[...] = U
-            U = out
-        return U, (Un.copy(), dt), dt
+        res = self.rng.standard_normal(Un.shape) if out is None else out
+        res[:, self.m] = U[:, self.m]
+        return res, (Un.copy(), dt), dt
 
     def step_vjp(self, Un, g, dt, kept=None):
         if kept is not None:
@@ -96,8 +99,12 @@ def test_last_segment_kept_by_the_forward_pass(k, nsteps):
     plain, keeping = OracleStepper(p), _KeepingStepper(p)
     UN, tape = rollout(plain, p.U0, nsteps, k)
     UNk, tapek = rollout(keeping, p.U0, nsteps, k, keep_last=True)
-    assert np.array_equal(UN, UNk, equal_nan=True) and tape.dts == tapek.dts
+    assert np.array_equal(UN[:, m], UNk[:, m]) and tape.dts == tapek.dts
     last = ((nsteps - 1) // k) * k
+    # U_N's guard cells are those of the state the kept segment starts from
+    # (the in-place steps before it), not the arbitrary ones of step_keep's
+    # fresh outputs
+    assert np.array_equal(UNk[:, ~m], tapek.checkpoints[last][:, ~m], equal_nan=True)
     assert sorted(tapek.tail) == list(range(last, nsteps))
     g = _loss_grad(p, UN, p.U0.copy(), m)
     ref = rollout_vjp(plain, tape, g)
@@ -109,3 +116,28 @@ def test_last_segment_kept_by_the_forward_pass(k, nsteps):
     # the kept segment is used once; a second backward pass recomputes it
     assert tapek.tail == {}
     assert np.array_equal(ref, rollout_vjp(keeping, tapek, g))
+
+
+def test_cfl_record_gating():
+    """The solver takes a step's dt from the maxima the previous step
+    recorded only for the tensor that step wrote, alive and unwritten by
+    torch since; a fresh copy (even one at a reused address), a tensor
+    written in place, or a forgotten record computes the dt from the state."""
+    import torch
+    from paper_2401_03378_amd import _hip
+    from paper_2401_03378_amd.solver import CflRecord
+    rec = CflRecord()
+    U = torch.zeros(4, 8, dtype=torch.float64)
+    assert rec.mode(U) == _hip.HYDRO_DT_RECORD          # nothing recorded yet
+    rec.wrote(U)
+    assert rec.mode(U) == _hip.HYDRO_DT_FROM_PREVIOUS
+    assert rec.mode(U.clone()) == _hip.HYDRO_DT_RECORD  # another tensor
+    U.add_(1.0)                                         # written through torch
+    assert rec.mode(U) == _hip.HYDRO_DT_RECORD
+    rec.wrote(U)
+    rec.forget()
+    assert rec.mode(U) == _hip.HYDRO_DT_RECORD
+    rec.wrote(U)
+    del U                                               # freed: the record dies with it
+    V = torch.zeros(4, 8, dtype=torch.float64)
+    assert rec.mode(V) == _hip.HYDRO_DT_RECORD
