@@ -266,12 +266,44 @@ int hydro_step_vjp(hydro_ctx_t *ctx, const double *Un, const double *dt_dev,
 int hydro_step_vjp_stages(hydro_ctx_t *ctx, const double *Un, const double *const *stages,
                           const double *dt_dev, const double *gUnext, double *gUn);
 
+/* The CFL time step of hydro_cfl_dt, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): no context and no allocation of any kind.  Its
+ * scratch, one double per block, is a fixed array inside the library
+ * (HYDRO_NOALLOC_MAX_BLOCKS doubles, 512 KiB, held on each GPU the library
+ * runs on until the process ends).
+ *   params      HOST pointer; ndim, gamma, cfl, dx, dy, dz are used and checked
+ *               as in hydro_validate (recon, rk, flags, weno_eps are ignored).
+ *   blocks_dev  DEVICE pointer to nblocks hydro_block_t entries, laid out as the host table's
+ *               are, 1 <= nblocks <= HYDRO_NOALLOC_MAX_BLOCKS; read only.
+ *   U           DEVICE state of nvar x ncell_total doubles (the layout above);
+ *               interiors are read.
+ *   dt_dev      DEVICE double that receives dt.
+ *   stream      hipStream_t (NULL: the default stream); asynchronous.
+ * On valid blocks and physical states dt equals hydro_cfl_dt's for the same
+ * problem bit for bit.  A block whose descriptor the kernel finds out of
+ * range (extents < 1, 2D nz != 1, offset < 0 or its padded cells beyond
+ * ncell_total; none of its cells is then read) or a non-physical cell
+ * (rho <= 0, p <= 0, NaN) makes dt NaN: with no context, that is the report.
+ * Returns HYDRO_EINVAL for a null pointer, bad params, nblocks out of range
+ * or ncell_total < 1 (text in hydro_last_error(NULL)), HYDRO_EHIP if the
+ * scratch cannot be resolved or a launch fails.  Every call on one GPU
+ * shares the scratch, which keeps the last call's contents: calls that
+ * overlap on one GPU (other streams or threads) race and must be ordered by
+ * the caller.  Each call writes the entries it reads, so none need
+ * clearing. */
+#define HYDRO_NOALLOC_MAX_BLOCKS 65536
+int hydro_cfl_dt_noalloc(const hydro_params_t *params, const hydro_block_t *blocks_dev, int32_t nblocks,
+                         int64_t ncell_total, const double *U, double *dt_dev, void *stream);
+
 /* Wait for the ctx's stream; *n_nonphys (may be NULL) receives the number of
  * non-physical events counted since the last call, then the count is reset.
  * Returns HYDRO_ENONPHYS if that number is non-zero. */
 int hydro_status(hydro_ctx_t *ctx, int64_t *n_nonphys);
 
-/* Text of the last error on this ctx (valid until the next call on it). */
+/* Text of the last error on this ctx (valid until the next call on it);
+ * with ctx NULL, of the last failed call without a context on this thread
+ * (hydro_create, hydro_create_amr, hydro_cfl_dt_noalloc). */
 const char *hydro_last_error(hydro_ctx_t *ctx);
 
 /* Wait for the ctx's stream, then release the ctx and all device memory it

@@ -22,7 +22,7 @@ EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create
            "hydro_set_tuning", "hydro_get_tuning",
            "hydro_fill_guards", "hydro_cfl_dt", "hydro_rk_stage", "hydro_step",
            "hydro_step_vjp", "hydro_step_vjp_stages", "hydro_status", "hydro_last_error", "hydro_destroy",
-           "hydro_fp_check")
+           "hydro_fp_check", "hydro_cfl_dt_noalloc")
 FLAG_LEVEL_BY_LEVEL = 1
 HYDRO_DT_FROM_PREVIOUS = 2
 HYDRO_DT_RECORD = 3
@@ -95,6 +95,7 @@ def lib():
             "hydro_last_error": (C.c_char_p, [vp]),
             "hydro_destroy": (None, [vp]),
             "hydro_fp_check": (C.c_int, [dp, dp, dp, dp, dp, dp, i64, vp]),
+            "hydro_cfl_dt_noalloc": (C.c_int, [C.POINTER(Params), dp, i32, i64, dp, dp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -162,3 +163,33 @@ def fp_check(a, b, c, stream=None):
     if rc != HYDRO_OK:
         raise HydroError(rc, "hydro_fp_check")
     return quot, root, fmad
+
+
+def block_table_bytes(prob) -> bytes:
+    """The problem's hydro_block_t table as raw bytes (the C layout), for a
+    caller that keeps the table in device memory (hydro_cfl_dt_noalloc)."""
+    _, B, _, nb = tables(prob)
+    return C.string_at(C.addressof(B), C.sizeof(Block) * nb)
+
+
+def cfl_dt_noalloc(prob, blocks_dev, U, dt, stream=None):
+    """hydro_cfl_dt_noalloc: the CFL dt of U into the device double dt,
+    with no context and no allocation.  blocks_dev is a CUDA uint8 tensor
+    holding block_table_bytes(prob); U and dt are contiguous float64 CUDA
+    tensors."""
+    import torch
+
+    for t in (U, dt):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("U and dt must be contiguous float64 CUDA tensors")
+    if blocks_dev.dtype != torch.uint8 or not blocks_dev.is_cuda or not blocks_dev.is_contiguous():
+        raise ValueError("blocks_dev must be a contiguous uint8 CUDA tensor")
+    P, _, _, nb = tables(prob)
+    if blocks_dev.numel() < C.sizeof(Block) * nb:
+        raise ValueError("blocks_dev is smaller than the block table")
+    st = stream if stream is not None else torch.cuda.current_stream(U.device)
+    rc = lib().hydro_cfl_dt_noalloc(C.byref(P), C.c_void_p(blocks_dev.data_ptr()), nb, int(prob.ncell),
+                                    C.c_void_p(U.data_ptr()), C.c_void_p(dt.data_ptr()),
+                                    C.c_void_p(st.cuda_stream))
+    if rc != HYDRO_OK:
+        raise HydroError(rc, lib().hydro_last_error(None).decode())

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhydro.so")
-SOURCES = ["hydro_fwd.hip", "hydro_vjp.hip", "hydro_api.hip"]
+SOURCES = ["hydro_fwd.hip", "hydro_vjp.hip", "hydro_api.hip", "hydro_noalloc.hip"]
 HEADERS = ["hydro_common.h", "hydro_kernels.h"]
 ARCH = os.environ.get("HYDRO_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",

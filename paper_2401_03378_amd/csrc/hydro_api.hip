@@ -995,7 +995,9 @@ int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks, co
     return check_problem(params, blocks, links, nblocks, ncell_total).empty() ? HYDRO_OK : HYDRO_EINVAL;
 }
 
-static thread_local std::string g_create_err;
+// Text of the last error of a call without a context (hydro_create,
+// hydro_create_amr, hydro_cfl_dt_noalloc), per thread.
+thread_local std::string g_noctx_err;
 
 int hydro_validate_amr(const hydro_params_t *params, const hydro_block_t *blocks, const hydro_link_t *links,
                        const hydro_amr_t *amr, int32_t nblocks, int64_t ncell_total)
@@ -1011,7 +1013,7 @@ static int create_ctx(const hydro_params_t *params, const hydro_block_t *blocks,
     std::string why = amr ? check_amr(params, blocks, links, amr, nblocks, ncell_total)
                           : check_problem(params, blocks, links, nblocks, ncell_total);
     if (!why.empty()) {
-        g_create_err = why;
+        g_noctx_err = why;
         return HYDRO_EINVAL;
     }
     hydro_ctx *c = new hydro_ctx();
@@ -1028,7 +1030,7 @@ static int create_ctx(const hydro_params_t *params, const hydro_block_t *blocks,
         for (int b = 0; b < nblocks; ++b) c->nlev = std::max(c->nlev, amr[b].level + 1);
     }
     auto bail = [&](int code) {
-        g_create_err = c->err;
+        g_noctx_err = c->err;
         hydro_destroy(c);
         return code;
     };
@@ -1097,7 +1099,7 @@ int hydro_create_amr(const hydro_params_t *params, const hydro_block_t *blocks, 
                      const hydro_amr_t *amr, int32_t nblocks, int64_t ncell_total, void *stream, hydro_ctx_t **out)
 {
     if (!amr && nblocks > 0) {
-        g_create_err = "null level table";
+        g_noctx_err = "null level table";
         return HYDRO_EINVAL;
     }
     hydro_amr_t none{};
@@ -1339,7 +1341,7 @@ int hydro_status(hydro_ctx_t *c, int64_t *n_nonphys)
 
 const char *hydro_last_error(hydro_ctx_t *c)
 {
-    if (!c) return g_create_err.c_str();
+    if (!c) return g_noctx_err.c_str();
     return c->err.c_str();
 }
 

@@ -114,3 +114,27 @@ def test_step_vjp_stages_rejects_null_arguments_without_a_gpu():
     assert L.hydro_step_vjp_stages(None, None, None, None, None, None) == _hip.HYDRO_EINVAL
     arr = (ctypes.c_void_p * 2)(None, None)
     assert L.hydro_step_vjp_stages(None, None, arr, None, None, None) == _hip.HYDRO_EINVAL
+
+
+def test_cfl_dt_noalloc_rejects_bad_arguments_without_a_gpu():
+    """hydro_cfl_dt_noalloc checks its arguments before any HIP call: null
+    pointers, bad params and block counts outside 1..HYDRO_NOALLOC_MAX_BLOCKS
+    are HYDRO_EINVAL, with text in hydro_last_error(NULL)."""
+    L = _hip.lib()
+    p = W.sod2d(N=32)
+    P, _, _, nb = _hip.tables(p)
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: every case fails validation first
+    f = L.hydro_cfl_dt_noalloc
+    assert f(None, fake, nb, p.ncell, fake, fake, None) == _hip.HYDRO_EINVAL
+    assert f(ctypes.byref(P), None, nb, p.ncell, fake, fake, None) == _hip.HYDRO_EINVAL
+    assert f(ctypes.byref(P), fake, nb, p.ncell, None, fake, None) == _hip.HYDRO_EINVAL
+    assert f(ctypes.byref(P), fake, nb, p.ncell, fake, None, None) == _hip.HYDRO_EINVAL
+    assert f(ctypes.byref(P), fake, 0, p.ncell, fake, fake, None) == _hip.HYDRO_EINVAL
+    assert f(ctypes.byref(P), fake, 65537, p.ncell, fake, fake, None) == _hip.HYDRO_EINVAL
+    assert b"HYDRO_NOALLOC_MAX_BLOCKS" in L.hydro_last_error(None)
+    assert f(ctypes.byref(P), fake, nb, 0, fake, fake, None) == _hip.HYDRO_EINVAL
+    for field, bad in (("gamma", 1.0), ("cfl", 0.0), ("dx", -1.0), ("ndim", 4)):
+        Q = _hip.Params.from_buffer_copy(P)
+        setattr(Q, field, bad)
+        assert f(ctypes.byref(Q), fake, nb, p.ncell, fake, fake, None) == _hip.HYDRO_EINVAL
+
