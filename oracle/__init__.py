@@ -23,6 +23,9 @@ ORA_OK, ORA_EINVAL, ORA_ENONPHYS, ORA_ENOMEM = 0, -1, -3, -4
 # Epsilon of the WENO5 nonlinear weights in Jiang & Shu (1996); a problem may
 # carry its own (attribute weno_eps).
 WENO_EPS = 1e-6
+# Optional physics: a uniform gravitational acceleration (attribute grav, a
+# 3-vector, or None) and the shock detector (attribute shock_thresh, or None).
+ORA_GRAVITY, ORA_SHOCK = 1, 2
 
 
 class OracleError(RuntimeError):
@@ -49,7 +52,8 @@ class _Problem(C.Structure):
                 ("nblocks", C.c_int32), ("ncell", C.c_int64),
                 ("gamma", C.c_double), ("cfl", C.c_double), ("dx", C.c_double),
                 ("dy", C.c_double), ("dz", C.c_double),
-                ("blocks", C.c_void_p), ("links", C.c_void_p), ("weno_eps", C.c_double)]
+                ("blocks", C.c_void_p), ("links", C.c_void_p), ("weno_eps", C.c_double),
+                ("grav", C.c_double * 3), ("shock_thresh", C.c_double), ("phys", C.c_int32)]
 
 
 _lib = None
@@ -79,6 +83,7 @@ def lib():
             "ora_weno5_n": (None, [i64, dp, C.c_double, dp, dp]),
             "ora_recon_cell_n": (None, [P, i64, dp, dp, dp, ip]),
             "ora_faces": (C.c_int, [P, dp, C.c_int, dp, dp, ip]),
+            "ora_shock_flags": (C.c_int, [P, dp, C.c_int, ip]),
             "ora_hllc_n": (C.c_int, [P, i64, C.c_int, dp, dp, dp, ip]),
             "ora_state_flux_n": (None, [P, i64, C.c_int, dp, dp, dp, dp]),
             "ora_eos_vjp_n": (None, [P, i64, dp, dp, dp]),
@@ -146,6 +151,16 @@ class Problem:
                           float(get("dx")), float(get("dy")), float(get("dz")),
                           C.cast(self._blocks, C.c_void_p), C.cast(self._links, C.c_void_p),
                           float(override.get("weno_eps", getattr(prob, "weno_eps", WENO_EPS))))
+        grav = override.get("grav", getattr(prob, "grav", None))
+        thresh = override.get("shock_thresh", getattr(prob, "shock_thresh", None))
+        if grav is not None:
+            g = [float(x) for x in grav] + [0.0] * (3 - len(grav))
+            for d in range(3):
+                self.c.grav[d] = g[d]
+            self.c.phys |= ORA_GRAVITY
+        if thresh is not None:
+            self.c.shock_thresh = float(thresh)
+            self.c.phys |= ORA_SHOCK
 
     @property
     def ptr(self):
@@ -322,6 +337,19 @@ def faces(prob, U, direction):
     fb = np.zeros(P.ncell, dtype=np.int32)
     _check(lib().ora_faces(P.ptr, _dp(U), int(direction), _dp(qm), _dp(qp), _ip(fb)), "faces")
     return qm, qp, fb
+
+
+def shock_flags(prob, U, direction, thresh=None):
+    """The shock detector's flags along a direction (the block initialisation
+    of a stage) for every interior cell of a guard-filled state U: (ncell,)
+    int32, 1 where flagged (0 elsewhere, padding included).  thresh
+    overrides the problem's shock_thresh."""
+    over = {} if thresh is None else {"shock_thresh": thresh}
+    P = prob if (isinstance(prob, Problem) and not over) else Problem(prob, **over)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    flag = np.zeros(P.ncell, dtype=np.int32)
+    _check(lib().ora_shock_flags(P.ptr, _dp(U), int(direction), _ip(flag)), "shock_flags")
+    return flag
 
 
 def hllc(prob, WL, WR, direction):

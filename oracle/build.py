@@ -13,13 +13,14 @@ SOURCES = ["oracle.c", "oracle_cs.c", "oracle_amr.c"]
 
 
 def build(verbose=False):
+    tmp = f"{LIB}.tmp{os.getpid()}"      # per process: concurrent test workers may build at once
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-std=gnu11", "-Wall", "-Wno-unknown-pragmas",
-           "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+           "-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 

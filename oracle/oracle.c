@@ -34,6 +34,11 @@ static int validate(const ora_problem *P)
     if (!(P->gamma > 1.0) || !(P->cfl > 0.0) || !(P->dx > 0.0) || !(P->dy > 0.0) || !(P->dz > 0.0))
         return ORA_EINVAL;
     if (!(P->weno_eps > 0.0) || !isfinite(P->weno_eps)) return ORA_EINVAL;
+    if (P->phys & ~(ORA_GRAVITY | ORA_SHOCK)) return ORA_EINVAL;
+    if ((P->phys & ORA_GRAVITY) &&
+        !(isfinite(P->grav[0]) && isfinite(P->grav[1]) && isfinite(P->grav[2])))
+        return ORA_EINVAL;
+    if ((P->phys & ORA_SHOCK) && !(P->shock_thresh >= 0.0 && isfinite(P->shock_thresh))) return ORA_EINVAL;
     int ngmin = (P->recon == 1) ? 3 : 2;
     /* extents, guard width, range of offsets */
     for (int b = 0; b < P->nblocks; b++) {
@@ -249,6 +254,9 @@ int ora_step_telescoping(const ora_problem *P, double *U, double *dt, int comput
 {
     int rc = validate(P);
     if (rc) return rc;
+    /* the telescoping listing runs the block initialisation (shockDet) once
+     * per step, before all stages: not built with the detector */
+    if (P->phys & ORA_SHOCK) return ORA_EINVAL;
     const int H = (P->recon == 1) ? 3 : 2, S = P->rk, ngt = tele_width(P);
     for (int b = 0; b < P->nblocks; b++)
         for (int d = 0; d < P->ndim; d++) {
@@ -544,6 +552,11 @@ static void hllc_vjp(const ora_problem *P, const double *WL, const double *WR, i
  * cotangents of every padded cell the block's stencils read. */
 static void block_rhs_vjp(const ora_problem *P, int b, const double *U, const double *gacc, double *gPad)
 {
+    unsigned char *shock = NULL;
+    if (P->phys & ORA_SHOCK) {
+        shock = malloc((size_t)(P->ndim * ora_r_npad(&P->blocks[b], P->ndim)));
+        ora_r_shock_detect(P, b, U, shock);
+    }
     const int nd = P->ndim, nv = nd + 2;
     const int64_t nc = P->ncell;
     const ora_block *B = &P->blocks[b];
@@ -574,9 +587,17 @@ static void block_rhs_vjp(const ora_problem *P, int b, const double *U, const do
                     for (int v = 0; v < nv; v++) Uln[5 * (t + 1 + R) + v] = U[v * nc + ci];
                     ora_r_eos(P, &Uln[5 * (t + 1 + R)], &W[5 * (t + 1 + R)]);
                 }
-                for (int t = -1; t <= n; t++)
-                    fb[t + 1] = ora_r_recon_cell(P, &W[5 * (t + 1 + R)], &qm[5 * (t + 1)], &qp[5 * (t + 1)],
+                for (int t = -1; t <= n; t++) {
+                    int sh = 0;
+                    if (shock) {
+                        int pos[3];
+                        pos[d] = t;  pos[o1] = e1;  pos[o2] = e2;
+                        if (nd == 2) pos[2] = 0;
+                        sh = shock[d * ora_r_npad(B, nd) + ora_r_cell(B, nd, pos[0], pos[1], pos[2]) - B->offset];
+                    }
+                    fb[t + 1] = ora_r_recon_cell(P, &W[5 * (t + 1 + R)], sh, &qm[5 * (t + 1)], &qp[5 * (t + 1)],
                                                  &code[5 * (t + 1)]);
+                }
                 /* reverse: flux differences -> face flux cotangents */
                 for (int i = 0; i < 5 * (n + 1); i++) gF[i] = 0.0;
                 for (int t = 0; t < n; t++) {
@@ -635,6 +656,7 @@ static void block_rhs_vjp(const ora_problem *P, int b, const double *U, const do
             }
     }
     free(Uln); free(W); free(gW); free(qm); free(qp); free(gqm); free(gqp); free(code); free(fb); free(gF);
+    free(shock);
 }
 
 /* Adjoint of guard filling: each guard cell's cotangent moves onto the
@@ -710,9 +732,23 @@ static void stage_vjp(const ora_problem *P, int s, double dt, const double *Us, 
             for (int j = 0; j < B->ny; j++)
                 for (int i = 0; i < B->nx; i++) {
                     int64_t ci = ora_r_cell(B, nd, i, j, k);
+                    /* gravity source: T_{m_d} gains dt rho g_d, T_E gains dt (m . g) */
+                    double gsrc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                    if (P->phys & ORA_GRAVITY) {
+                        double g[3];
+                        ora_r_grav_accel(P, b, i, j, k, g);
+                        double gTE = bcoef * gOut[(nd + 1) * nc + ci];
+                        for (int d = 0; d < nd; d++) {
+                            double gTm = bcoef * gOut[(1 + d) * nc + ci];
+                            gsrc[0] += dt * (g[d] * gTm);
+                            gsrc[1 + d] = dt * (g[d] * gTE);
+                        }
+                    }
                     for (int v = 0; v < nv; v++) {
                         double go = gOut[v * nc + ci];
-                        gUs[v * nc + ci] = bcoef * go + gPad[v * nc + ci];
+                        double gs = bcoef * go + gPad[v * nc + ci];
+                        if (P->phys & ORA_GRAVITY) gs = gs + gsrc[v];
+                        gUs[v * nc + ci] = gs;
                         gUn[v * nc + ci] += a * go;
                     }
                 }
@@ -793,7 +829,7 @@ void ora_recon_cell_n(const ora_problem *P, int64_t n, const double *w, double *
 {
     const int R = (P->recon == 1) ? 2 : 1;
     for (int64_t i = 0; i < n; i++)
-        fb[i] = ora_r_recon_cell(P, &w[5 * ((2 * R + 1) * i + R)], &qm[5 * i], &qp[5 * i], NULL);
+        fb[i] = ora_r_recon_cell(P, &w[5 * ((2 * R + 1) * i + R)], 0, &qm[5 * i], &qp[5 * i], NULL);
 }
 
 /* Face values of every interior cell along direction d, from a state whose
@@ -815,6 +851,11 @@ int ora_faces(const ora_problem *P, const double *U, int d, double *qm, double *
         int n = ora_r_extent(B, d);
         int o1 = (d == 0) ? 1 : 0, o2 = (d == 2) ? 1 : 2;
         int n1 = ora_r_extent(B, o1), n2 = (nd == 3) ? ora_r_extent(B, o2) : 1;
+        unsigned char *shock = NULL;
+        if (P->phys & ORA_SHOCK) {
+            shock = malloc((size_t)(nd * ora_r_npad(B, nd)));
+            ora_r_shock_detect(P, b, U, shock);
+        }
         double *W = malloc(sizeof(double) * 5 * (n + 2 * R));
         for (int e2 = 0; e2 < n2; e2++)
             for (int e1 = 0; e1 < n1; e1++) {
@@ -832,13 +873,41 @@ int ora_faces(const ora_problem *P, const double *U, int d, double *qm, double *
                     if (nd == 2) pos[2] = 0;
                     int64_t ci = ora_r_cell(B, nd, pos[0], pos[1], pos[2]);
                     double m[5], p[5];
-                    fb[ci] = ora_r_recon_cell(P, &W[5 * (t + R)], m, p, NULL);
+                    int sh = shock ? shock[d * ora_r_npad(B, nd) + ci - B->offset] : 0;
+                    fb[ci] = ora_r_recon_cell(P, &W[5 * (t + R)], sh, m, p, NULL);
                     for (int q = 0; q < 5; q++) { qm[q * nc + ci] = m[q]; qp[q * nc + ci] = p[q]; }
                 }
             }
         free(W);
+        free(shock);
     }
     return bad ? ORA_ENONPHYS : ORA_OK;
+}
+
+/* The shock detector's flags along direction d (the block initialisation of
+ * a stage) for every interior cell of a guard-filled state: flag (ncell)
+ * receives 1 or 0 in the interior; other entries are left as they are.  The
+ * problem's shock_thresh is used whether or not ORA_SHOCK is set. */
+int ora_shock_flags(const ora_problem *P, const double *U, int d, int *flag)
+{
+    int rc = validate(P);
+    if (rc) return rc;
+    if (d < 0 || d >= P->ndim || !(P->shock_thresh >= 0.0)) return ORA_EINVAL;
+    const int nd = P->ndim;
+    for (int b = 0; b < P->nblocks; b++) {
+        const ora_block *B = &P->blocks[b];
+        const int64_t np = ora_r_npad(B, nd);
+        unsigned char *sh = malloc((size_t)(nd * np));
+        ora_r_shock_detect(P, b, U, sh);
+        for (int k = 0; k < B->nz; k++)
+            for (int j = 0; j < B->ny; j++)
+                for (int i = 0; i < B->nx; i++) {
+                    int64_t ci = ora_r_cell(B, nd, i, j, k);
+                    flag[ci] = sh[d * np + ci - B->offset];
+                }
+        free(sh);
+    }
+    return ORA_OK;
 }
 
 int ora_hllc_n(const ora_problem *P, int64_t n, int dir, const double *WL, const double *WR, double *F, int *tape)

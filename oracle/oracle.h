@@ -37,7 +37,16 @@ typedef struct {
     const ora_block *blocks;
     const ora_link *links;
     double weno_eps;        /* epsilon of the WENO5 weights (Jiang & Shu: 1e-6) */
+    double grav[3];         /* uniform gravitational acceleration (ORA_GRAVITY; z ignored in 2D) */
+    double shock_thresh;    /* relative pressure jump of the shock detector (ORA_SHOCK), >= 0 */
+    int32_t phys;           /* ORA_GRAVITY | ORA_SHOCK, or 0 */
 } ora_problem;
+
+/* Optional parts of the intra-stage chain and the block initialisation
+ * (the grvAccel and shockDet nodes of the paper's Algorithms "Intra stage
+ * calculations for Spark" and "Block initializations for Spark"). */
+#define ORA_GRAVITY 1
+#define ORA_SHOCK 2
 
 /* Two-level-ratio block AMR (refinement ratio 2, levels differ by at most
  * one across a face).  A face whose link is ORA_LEVEL_FACE touches blocks of

@@ -82,6 +82,7 @@ static int amr_validate(const ora_problem *P, const ora_amr *A, amr_base *base)
     if (rc) return rc;
     rc = ora_validate(&base->Q);
     if (rc) return rc;
+    if (P->phys) return ORA_EINVAL;     /* gravity and the shock detector: meshes without levels only */
     const int nd = P->ndim;
     for (int b = 0; b < P->nblocks; b++) {
         const ora_block *B = &P->blocks[b], *B0 = &P->blocks[0];
@@ -228,7 +229,7 @@ static int64_t block_update(const ora_problem *Q, const ora_amr *A, int b, int s
     rk_coeffs(Q->rk, s, &a, &bcoef);
     const int64_t nint = (int64_t)B->nx * B->ny * B->nz;
     double *acc = malloc(sizeof(double) * nv * nint);
-    int64_t bad = ora_a_block_rhs(&L, b, Us, acc, bflux);
+    int64_t bad = ora_a_block_rhs(&L, b, Us, NULL, acc, bflux);
     for (int k = 0; k < B->nz; k++)
         for (int j = 0; j < B->ny; j++)
             for (int i = 0; i < B->nx; i++) {

@@ -65,6 +65,8 @@ class Problem:
     amr: Optional[np.ndarray] = None   # AMR_DTYPE per block, for meshes with refinement levels
     origin: Optional[np.ndarray] = None   # (nblocks, 3) lower corner of each block (AMR meshes)
     weno_eps: float = 1e-6   # epsilon of the WENO5 nonlinear weights (Jiang & Shu 1996)
+    grav: Optional[tuple] = None          # uniform gravitational acceleration (gx, gy, gz), or None
+    shock_thresh: Optional[float] = None  # relative pressure jump of the shock detector, or None (off)
 
     @property
     def nvar(self) -> int:
@@ -380,6 +382,47 @@ def random_blocks(ndim, sizes, ng, seed, recon=PLM_MC, rk=2, gamma=1.4, cfl=0.8,
     return Problem("random", ndim, recon, rk, gamma, cfl, dx, dx,
                    dx if ndim == 3 else 1.0, blocks, links, ncell, 1, U, seed,
                    (NB[0], NB[1], NB[2], n))
+
+
+def free_fall(ndim, n=8, ng=2, recon=PLM_MC, rk=2, NB=None, grav=(0.3, -2.0, 0.5), rho=1.3,
+              vel=(0.2, -0.1, 0.3), p=0.7, gamma=1.4, cfl=0.8):
+    """A uniform gas in a periodic box under a uniform gravitational
+    acceleration: every cell holds the same (rho, u, p)."""
+    if NB is None:
+        NB = (2, 2, 2 if ndim == 3 else 1)
+    blocks, links, ncell = uniform_grid(NB, n, ng, ndim, "periodic")
+    nz = n * NB[2] if ndim == 3 else 1
+    shp = (nz, n * NB[1], n * NB[0])
+    G = conserved(np.full(shp, rho), [np.full(shp, v) for v in vel[:ndim]], np.full(shp, p), gamma)
+    U = empty_state(ndim + 2, ncell)
+    scatter_global(U, G, blocks, (NB[0], NB[1], NB[2], n), ndim)
+    dx = 1.0 / (n * NB[0])
+    return Problem("free_fall", ndim, recon, rk, gamma, cfl, dx, dx, dx if ndim == 3 else 1.0,
+                   blocks, links, ncell, 1, U, None, (NB[0], NB[1], NB[2], n), grav=tuple(grav))
+
+
+def atmosphere2d(N=64, n=16, ng=2, g=1.0, recon=PLM_MC, rk=2, gamma=1.4, cfl=0.8):
+    """Isothermal atmosphere at rest in the unit square: rho = p = exp(-g y)
+    at cell centres (hydrostatic for an acceleration of g along -y), periodic
+    along x, outflow at the bottom and top faces."""
+    NB = N // n
+    blocks, links, ncell = uniform_grid((NB, NB, 1), n, ng, 2, "periodic")
+    for b in range(len(links)):
+        nbr = links[b]["nbr"].copy()
+        bj = (b // NB) % NB
+        if bj == 0:
+            nbr[2] = OUTFLOW
+        if bj == NB - 1:
+            nbr[3] = OUTFLOW
+        links[b]["nbr"] = nbr
+    yc = (np.arange(N) + 0.5) / N
+    rho = np.broadcast_to(np.exp(-g * yc)[:, None], (N, N)).copy()
+    z = np.zeros((N, N))
+    G = conserved(rho, [z, z], rho.copy(), gamma)[:, None]
+    U = empty_state(4, ncell)
+    scatter_global(U, G, blocks, (NB, NB, 1, n), 2)
+    return Problem("atmosphere2d", 2, recon, rk, gamma, cfl, 1.0 / N, 1.0 / N, 1.0,
+                   blocks, links, ncell, 1, U, None, (NB, NB, 1, n), grav=(0.0, -g, 0.0))
 
 
 def amr_mesh(ndim, NBc, n, ng, refine, bc="periodic"):

@@ -199,24 +199,24 @@ def test_sedov_fallback_fires():
 
 # ---------------------------------------------------------------- mutations
 
-_FALLBACK = """    int fb = !(RE(qm[0]) > 0.0 && RE(qm[4]) > 0.0) || !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
+_FALLBACK = """    int fb = shock || !(RE(qm[0]) > 0.0 && RE(qm[4]) > 0.0) || !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
     if (fb)
         for (int q = 0; q < 5; q++) { qm[q] = w[q]; qp[q] = w[q]; }"""
 
 MUTATIONS = {
     "offending_face_only": """    int fbm = !(RE(qm[0]) > 0.0 && RE(qm[4]) > 0.0), fbp = !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
-    int fb = fbm || fbp;
+    int fb = shock || fbm || fbp;
     for (int q = 0; q < 5; q++) { if (fbm) qm[q] = w[q]; if (fbp) qp[q] = w[q]; }""",
-    "density_and_pressure_only": """    int fb = !(RE(qm[0]) > 0.0 && RE(qm[4]) > 0.0) || !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
+    "density_and_pressure_only": """    int fb = shock || !(RE(qm[0]) > 0.0 && RE(qm[4]) > 0.0) || !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
     if (fb)
         for (int q = 0; q < 5; q += 4) { qm[q] = w[q]; qp[q] = w[q]; }""",
-    "neighbour_states": """    int fb = !(RE(qm[0]) > 0.0 && RE(qm[4]) > 0.0) || !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
+    "neighbour_states": """    int fb = shock || !(RE(qm[0]) > 0.0 && RE(qm[4]) > 0.0) || !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
     if (fb)
         for (int q = 0; q < 5; q++) { qm[q] = w[q - 5]; qp[q] = w[q + 5]; }""",
-    "pressure_test_only": """    int fb = !(RE(qm[4]) > 0.0) || !(RE(qp[4]) > 0.0);
+    "pressure_test_only": """    int fb = shock || !(RE(qm[4]) > 0.0) || !(RE(qp[4]) > 0.0);
     if (fb)
         for (int q = 0; q < 5; q++) { qm[q] = w[q]; qp[q] = w[q]; }""",
-    "right_face_test_only": """    int fb = !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
+    "right_face_test_only": """    int fb = shock || !(RE(qp[0]) > 0.0 && RE(qp[4]) > 0.0);
     if (fb)
         for (int q = 0; q < 5; q++) { qm[q] = w[q]; qp[q] = w[q]; }""",
 }
