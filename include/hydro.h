@@ -76,13 +76,44 @@ typedef struct {
     int32_t ndim;     /* 2 or 3 */
     int32_t recon;    /* HYDRO_PLM_MC (needs ng >= 2) or HYDRO_WENO5 (ng >= 3) */
     int32_t rk;       /* 2 or 3 SSP-RK stages */
-    int32_t flags;    /* 0, or HYDRO_FLAG_LEVEL_BY_LEVEL for an AMR context */
+    int32_t flags;    /* 0 or an OR of HYDRO_FLAG_LEVEL_BY_LEVEL (AMR context),
+                         HYDRO_FLAG_GRAVITY, HYDRO_FLAG_SHOCK_DETECT */
     double gamma;     /* ratio of specific heats, > 1 */
     double cfl;       /* Courant number of the unsplit sum, > 0 */
     double dx, dy, dz;  /* cell widths (dz ignored in 2D but must be > 0) */
     double weno_eps;  /* epsilon of the WENO5 nonlinear weights alpha_k = d_k/(eps+beta_k)^2,
                          finite and > 0 (Jiang & Shu 1996 use 1e-6); ignored by PLM-MC */
+    double grav[3];   /* HYDRO_FLAG_GRAVITY: uniform gravitational acceleration (finite;
+                         grav[2] unused in 2D) */
+    double shock_thresh;  /* HYDRO_FLAG_SHOCK_DETECT: relative pressure jump, finite and >= 0 */
 } hydro_params_t;
+
+/* Gravity (the grvAccel node that heads the paper's Algorithm "Intra stage
+ * calculations for Spark"; the paper gives no field).  The acceleration is
+ * the uniform vector grav, and its source enters the update of every stage
+ * from the stage input's own cell values: L(U_s) gains rho g_d in momentum d
+ * and (m_x g_x + m_y g_y) + m_z g_z in energy (2D: m_x g_x + m_y g_y), as
+ * L_v = S_v - (flux differences)_v for v >= 1.  The CFL dt is unchanged.
+ *
+ * Shock detector (the shockDet node of the paper's Algorithm "Block
+ * initializations for Spark", which the non-telescoping RK listing of Sec.
+ * 4.2 runs per stage before the intra-stage chain; no formula in the paper).
+ * From the stage input's primitives, a cell is flagged along direction d
+ * when u_d(next) - u_d(previous) < 0 (compression along d) and
+ * |p(next) - p(previous)| > shock_thresh * min(p(previous), p(next)); a
+ * flagged cell reconstructs at first order along d (both faces take its own
+ * primitives, as the positivity fallback does).  Per direction, because the
+ * cells just outside a block face would need edge cells for a divergence.
+ *
+ * Both apply to meshes without levels in the persistent, per-block and
+ * materialised modes, and to hydro_step_vjp / hydro_step_vjp_stages.
+ * Gravity also applies in HYDRO_MODE_TELESCOPING; the detector does not
+ * (that listing runs the block initialisation once per step), and
+ * hydro_set_tuning refuses the telescoping mode for it; hydro_create_amr
+ * refuses either flag.  Stages with either flag run the plain schedule
+ * whatever hydro_tuning_t.variant says. */
+#define HYDRO_FLAG_GRAVITY 2
+#define HYDRO_FLAG_SHOCK_DETECT 4
 
 /* Refinement levels (hydro_create_amr).  Flash-X's block-structured AMR
  * (the paper's Sec. 2.2 mesh and Sec. 4.2 flux-correction listings) with

@@ -24,6 +24,8 @@ EXPORTS = ("hydro_validate", "hydro_create", "hydro_validate_amr", "hydro_create
            "hydro_step_vjp", "hydro_step_vjp_stages", "hydro_status", "hydro_last_error", "hydro_destroy",
            "hydro_fp_check", "hydro_cfl_dt_noalloc")
 FLAG_LEVEL_BY_LEVEL = 1
+FLAG_GRAVITY = 2          # uniform gravitational acceleration (problem attribute grav)
+FLAG_SHOCK_DETECT = 4     # shock detector (problem attribute shock_thresh)
 HYDRO_DT_FROM_PREVIOUS = 2
 HYDRO_DT_RECORD = 3
 WENO_EPS = 1e-6          # Jiang & Shu's epsilon, the default of a problem without weno_eps
@@ -52,7 +54,7 @@ class Params(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("recon", C.c_int32), ("rk", C.c_int32),
                 ("flags", C.c_int32), ("gamma", C.c_double), ("cfl", C.c_double),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
-                ("weno_eps", C.c_double)]
+                ("weno_eps", C.c_double), ("grav", C.c_double * 3), ("shock_thresh", C.c_double)]
 
 
 class Tuning(C.Structure):
@@ -120,6 +122,16 @@ def tables(prob):
     P = Params(int(prob.ndim), int(prob.recon), int(prob.rk), 0, float(prob.gamma),
                float(prob.cfl), float(prob.dx), float(prob.dy), float(prob.dz),
                float(getattr(prob, "weno_eps", WENO_EPS)))
+    grav = getattr(prob, "grav", None)
+    if grav is not None:
+        g = [float(x) for x in grav] + [0.0] * (3 - len(grav))
+        for d in range(3):
+            P.grav[d] = g[d]
+        P.flags |= FLAG_GRAVITY
+    thresh = getattr(prob, "shock_thresh", None)
+    if thresh is not None:
+        P.shock_thresh = float(thresh)
+        P.flags |= FLAG_SHOCK_DETECT
     return P, B, L, nb
 
 

@@ -129,6 +129,12 @@ std::string check_problem(const hydro_params_t *p, const hydro_block_t *blocks, 
     if (!(p->gamma > 1.0)) return "gamma must be > 1";
     if (!(p->cfl > 0.0) || !(p->dx > 0.0) || !(p->dy > 0.0) || !(p->dz > 0.0)) return "cfl and cell widths must be > 0";
     if (!(p->weno_eps > 0.0) || !std::isfinite(p->weno_eps)) return "weno_eps must be finite and > 0";
+    if (p->flags & ~(HYDRO_FLAG_LEVEL_BY_LEVEL | HYDRO_FLAG_GRAVITY | HYDRO_FLAG_SHOCK_DETECT)) return "unknown flags";
+    if ((p->flags & HYDRO_FLAG_GRAVITY) &&
+        !(std::isfinite(p->grav[0]) && std::isfinite(p->grav[1]) && std::isfinite(p->grav[2])))
+        return "grav must be finite";
+    if ((p->flags & HYDRO_FLAG_SHOCK_DETECT) && !(p->shock_thresh >= 0.0 && std::isfinite(p->shock_thresh)))
+        return "shock_thresh must be finite and >= 0";
     const int ngmin = (p->recon == HYDRO_WENO5) ? 3 : 2;
     std::vector<std::pair<int64_t, int64_t>> span(nblocks);
     for (int b = 0; b < nblocks; ++b) {
@@ -169,6 +175,8 @@ std::string check_amr(const hydro_params_t *p, const hydro_block_t *blocks, cons
 {
     if (!p) return "null params";
     if (nblocks > 0 && (!blocks || !links || !amr)) return "null descriptor table";
+    if (p->flags & (HYDRO_FLAG_GRAVITY | HYDRO_FLAG_SHOCK_DETECT))
+        return "gravity and the shock detector apply to meshes without levels only";
     if (p->flags & ~HYDRO_FLAG_LEVEL_BY_LEVEL) return "unknown flags";
     const int nd = p->ndim;
     std::vector<hydro_link_t> same(links, links + std::max(0, nblocks));
@@ -433,6 +441,22 @@ void rk_coeffs(int rk, int s, double &a, double &b)
     if (rk == 3 && s == 3) { a = 1.0 / 3.0; b = 2.0 / 3.0; }
 }
 
+// Gravity and the shock detector of a problem (kGravity | kShock).
+void phys_args(const hydro_ctx *c, int32_t &phys, double (&grav)[3], double &sthresh)
+{
+    phys = 0;
+    grav[0] = grav[1] = grav[2] = 0.0;
+    sthresh = 0.0;
+    if (c->prm.flags & HYDRO_FLAG_GRAVITY) {
+        phys |= kGravity;
+        for (int d = 0; d < 3; ++d) grav[d] = c->prm.grav[d];
+    }
+    if (c->prm.flags & HYDRO_FLAG_SHOCK_DETECT) {
+        phys |= kShock;
+        sthresh = c->prm.shock_thresh;
+    }
+}
+
 StageArgs stage_args(hydro_ctx *c, int s, const double *dt, const double *Un, const double *Us, double *Uout)
 {
     StageArgs a{};
@@ -457,6 +481,7 @@ StageArgs stage_args(hydro_ctx *c, int s, const double *dt, const double *Un, co
     a.nbad = c->d_nbad;
     a.freg = c->d_freg;
     a.nface = c->nface;
+    phys_args(c, a.phys, a.grav, a.sthresh);
     return a;
 }
 
@@ -1117,6 +1142,9 @@ int hydro_set_tuning(hydro_ctx_t *c, const hydro_tuning_t *t)
         return fail(c, HYDRO_EINVAL, "tuning range");
     if (c->amr && t->mode != HYDRO_MODE_PERSISTENT)
         return fail(c, HYDRO_EINVAL, "a mesh with refinement levels runs in the persistent mode only");
+    if ((c->prm.flags & HYDRO_FLAG_SHOCK_DETECT) && t->mode == HYDRO_MODE_TELESCOPING)
+        return fail(c, HYDRO_EINVAL, "the telescoping step runs the block initialisation (shock detector) once "
+                                     "per step: not built with the detector");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     const int old_tile = c->tune.tile;
@@ -1304,6 +1332,7 @@ static int step_vjp(hydro_ctx_t *c, const double *Un, const double *const *stage
         v.nxitems = c->nxitems;
         v.UsT = UsT;
         v.gOutT = gOutT;
+        phys_args(c, v.phys, v.grav, v.sthresh);
         hipError_t ex = launch_vjp_xpose(v, nd, c->prm.recon, st);
         if (ex != hipSuccess) return hip_fail(c, ex, "adjoint transpose launch");
         hipError_t el = launch_vjp_lines(v, nd, c->prm.recon, c->nlines, st);

@@ -15,6 +15,9 @@ namespace hydro {
 
 constexpr int kPLM = 0;
 constexpr int kWENO = 1;
+// optional parts of a stage: gravity source, shock detector
+constexpr int kGravity = 1;
+constexpr int kShock = 2;
 
 // Geometry of one block as the kernels see it.
 struct DevBlock {
@@ -171,12 +174,42 @@ __device__ __forceinline__ void weno5(double a, double b, double c, double d, do
     }
 }
 
+// Shock detector of the middle cell of a line stencil s (2R+1 cells along
+// direction D): compression along D (u_D of the next cell below u_D of the
+// previous one) and a pressure jump across the cell larger than thresh times
+// the smaller of the two pressures.
+template <int D, int R, int S>
+__device__ __forceinline__ bool shock_flag(const double (&s)[S][5], double thresh)
+{
+    const double du = s[R + 1][1 + D] - s[R - 1][1 + D];
+    const double pa = s[R - 1][4], pb = s[R + 1][4];
+    const double jump = fabs(pb - pa);
+    const double lim = thresh * dmin(pa, pb);
+    return (du < 0.0) && (jump > lim);
+}
+
+// The same along x (y = false) or y (y = true), chosen at run time.
+template <int R, int S>
+__device__ __forceinline__ bool shock_flag_xy(const double (&s)[S][5], bool y, double thresh)
+{
+    const double dux = s[R + 1][1] - s[R - 1][1];
+    const double duy = s[R + 1][2] - s[R - 1][2];
+    const double du = y ? duy : dux;
+    const double pa = s[R - 1][4], pb = s[R + 1][4];
+    const double jump = fabs(pb - pa);
+    const double lim = thresh * dmin(pa, pb);
+    return (du < 0.0) && (jump > lim);
+}
+
 // Reconstruct all primitives of one cell along a line; s[c][v] is the
 // stencil (2R+1 cells).  Applies the positivity fallback (both faces become
-// the cell value when either face has non-positive density or pressure).
-// Returns true if the fallback fired.  eps: the WENO5 weight epsilon.
+// the cell value when either face has non-positive density or pressure);
+// a cell the shock detector flagged along this line (shock) takes the same
+// first-order faces.  Returns true if the faces are first order.  eps: the
+// WENO5 weight epsilon.
 template <int NDIM, int RECON, int S>
-__device__ __forceinline__ bool recon_cell(const double (&s)[S][5], double (&qm)[5], double (&qp)[5], double eps)
+__device__ __forceinline__ bool recon_cell(const double (&s)[S][5], double (&qm)[5], double (&qp)[5], double eps,
+                                           bool shock = false)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
 #pragma unroll
@@ -187,7 +220,7 @@ __device__ __forceinline__ bool recon_cell(const double (&s)[S][5], double (&qm)
         else
             plm(s[R - 1][v], s[R][v], s[R + 1][v], qm[v], qp[v]);
     }
-    const bool fb = !(qm[0] > 0.0 && qm[4] > 0.0) || !(qp[0] > 0.0 && qp[4] > 0.0);
+    const bool fb = shock || !(qm[0] > 0.0 && qm[4] > 0.0) || !(qp[0] > 0.0 && qp[4] > 0.0);
     if (fb) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) { qm[v] = s[R][v]; qp[v] = s[R][v]; }

@@ -44,7 +44,8 @@ __device__ __forceinline__ void set_prio(int p)
     else __builtin_amdgcn_s_setprio(0);
 }
 
-template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF, bool LV = false, bool CFLO = false>
+template <int NDIM, int RECON, int TX, int TY, bool GATHER, bool PF, bool LV = false, bool CFLO = false,
+          bool PHYS = false>
 __device__ __forceinline__ void stage_body(const StageArgs &A)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
@@ -65,6 +66,10 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
     const Consts K{A.gamma, A.g1, A.ig1};
     const double dt = *A.dt;
     bool bad = false;
+    // PHYS: the shock detector's flags decide first-order faces; gravity adds
+    // its source in the update (both uniform over the launch)
+    const bool shk = PHYS && (A.phys & kShock);
+    const bool grv = PHYS && (A.phys & kGravity);
     // CFLO: each thread's maximum of the CFL wave-speed sum of the cells it writes
     __shared__ double sCfl[CFLO ? NT : 1];
     if constexpr (CFLO) sCfl[tid] = 0.0;
@@ -149,8 +154,8 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) { s0[c][v] = Wt[c][v]; s1[c][v] = Wt[c + 1][v]; }
                 double qa[5], qb[5], qm[5];
-                recon_cell<NDIM, RECON>(s0, qa, qpz, A.eps);      // cell z0-1: keep its right face
-                recon_cell<NDIM, RECON>(s1, qm, qb, A.eps);       // cell z0
+                recon_cell<NDIM, RECON>(s0, qa, qpz, A.eps, shk && shock_flag<2, R>(s0, A.sthresh));  // cell z0-1: keep its right face
+                recon_cell<NDIM, RECON>(s1, qm, qb, A.eps, shk && shock_flag<2, R>(s1, A.sthresh));   // cell z0
                 bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Flo, K);
                 if (z0 == 0) reg_put(4, i, j, Flo);
 #pragma unroll
@@ -194,7 +199,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = zw[R - 1][v];
                     double qm[5], qp[5], Fhi[5];
-                    recon_cell<NDIM, RECON>(zw, qm, qp, A.eps);   // cell k+1
+                    recon_cell<NDIM, RECON>(zw, qm, qp, A.eps, shk && shock_flag<2, R>(zw, A.sthresh));   // cell k+1
                     bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Fhi, K);
                     if (k == B.nz - 1) reg_put(5, i, j, Fhi);
 #pragma unroll
@@ -266,14 +271,14 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 for (int c = 0; c < NW; ++c)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) s[c][v] = sW[v][ty + H][tx + H - R + c];
-                recon_cell<NDIM, RECON>(s, qmx, qp, A.eps);
+                recon_cell<NDIM, RECON>(s, qmx, qp, A.eps, shk && shock_flag<0, R>(s, A.sthresh));
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sQx[v][ty][tx + 1] = qp[v];
 #pragma unroll
                 for (int c = 0; c < NW; ++c)
 #pragma unroll
                     for (int v = 0; v < 5; ++v) s[c][v] = sW[v][ty + H - R + c][tx + H];
-                recon_cell<NDIM, RECON>(s, qmy, qp, A.eps);
+                recon_cell<NDIM, RECON>(s, qmy, qp, A.eps, shk && shock_flag<1, R>(s, A.sthresh));
 #pragma unroll
                 for (int v = 0; v < 5; ++v) sQy[v][ty + 1][tx] = qp[v];
             }
@@ -299,7 +304,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
 #pragma unroll
                         for (int v = 0; v < 5; ++v) s[c][v] = sW[v][cy + H - R + c][epos + H];
                 }
-                recon_cell<NDIM, RECON>(s, qm, qp, A.eps);
+                recon_cell<NDIM, RECON>(s, qm, qp, A.eps, shk && shock_flag_xy<R>(s, etype >= 2, A.sthresh));
                 if (etype == 0) {
 #pragma unroll
                     for (int v = 0; v < 5; ++v) sQx[v][epos][0] = qp[v];
@@ -371,13 +376,22 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
             // flux differences and the SSP-RK combination
             if (own) {
                 const int64_t ci = cell_at(B, i, j, k);
+                // gravity source from the stage input's cell: rho g_d, m . g
+                double src[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                if (grv) {
+#pragma unroll
+                    for (int d = 0; d < NDIM; ++d) src[1 + d] = cus[0] * A.grav[d];
+                    double mg = cus[1] * A.grav[0] + cus[2] * A.grav[1];
+                    if constexpr (NDIM == 3) mg = mg + cus[3] * A.grav[2];
+                    src[NV - 1] = mg;
+                }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     const double Dx = sFx[v][ty][tx + 1] - sFx[v][ty][tx];
                     const double Dy = sFy[v][ty + 1][tx] - sFy[v][ty][tx];
                     double acc = Dx * idxb + Dy * idyb;
                     if constexpr (NDIM == 3) acc = acc + Dz[v] * idzb;
-                    const double L = -acc;
+                    const double L = (grv && v > 0) ? src[v] - acc : -acc;
                     const double T = fma(dt, L, cus[v]);
                     double out;
                     if (A.stage == 1)
@@ -441,6 +455,20 @@ template <int NDIM, int RECON, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))) k_stage_cfl(StageArgs A)
 {
     stage_body<NDIM, RECON, TX, TY, true, false, false, true>(A);
+}
+
+// Stages with gravity or the shock detector: the plain schedule (and its
+// form that records the CFL maxima) with those parts compiled in.
+template <int NDIM, int RECON, int TX, int TY, bool GATHER>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))) k_stage_phys(StageArgs A)
+{
+    stage_body<NDIM, RECON, TX, TY, GATHER, false, false, false, true>(A);
+}
+
+template <int NDIM, int RECON, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(2))) k_stage_cfl_phys(StageArgs A)
+{
+    stage_body<NDIM, RECON, TX, TY, true, false, false, true, true>(A);
 }
 
 // Meshes with refinement levels: the plain schedule that also writes the
@@ -760,6 +788,16 @@ hipError_t launch_tele_copy(const TeleArgs &a, int ndim, int nblk, bool to_thick
 template <int NDIM, int RECON, int TX, int TY, bool GATHER>
 static hipError_t launch_stage_t(const StageArgs &a, int variant, int grid, hipStream_t st)
 {
+    if (a.phys) {           // meshes without levels only (the context refuses the rest)
+        if constexpr (GATHER) {
+            if (a.cfl_partial != nullptr) {
+                k_stage_cfl_phys<NDIM, RECON, TX, TY><<<grid, TX * TY, 0, st>>>(a);
+                return hipGetLastError();
+            }
+        }
+        k_stage_phys<NDIM, RECON, TX, TY, GATHER><<<grid, TX * TY, 0, st>>>(a);
+        return hipGetLastError();
+    }
     if constexpr (GATHER) {
         if (a.freg != nullptr) {
             k_stage_lv<NDIM, RECON, TX, TY><<<grid, TX * TY, 0, st>>>(a);

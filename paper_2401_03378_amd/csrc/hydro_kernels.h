@@ -23,6 +23,9 @@ struct StageArgs {
     double *freg;               // flux registers (faces with FaceSrc::reg >= 0)
     int32_t nface;              // cells per register slot and variable
     double *cfl_partial;        // non-null: per-workgroup maxima of the CFL wave-speed sum of Uout
+    int32_t phys;               // kGravity | kShock, or 0
+    double grav[3];             // uniform gravitational acceleration (kGravity)
+    double sthresh;             // relative pressure jump of the shock detector (kShock)
 };
 
 // Coarse-fine faces: guard fill across levels and the flux correction.
@@ -99,6 +102,9 @@ struct VjpArgs {
     int32_t nxitems;
     double *UsT;                // Us along x lines, j fastest (positions -H .. nx+H-1)
     double *gOutT;              // gOut along x lines, j fastest (interior positions)
+    int32_t phys;               // kGravity | kShock, or 0 (as StageArgs)
+    double grav[3];
+    double sthresh;
 };
 
 hipError_t launch_stage(const StageArgs &a, int ndim, int recon, int tile, int variant, bool gather, int grid,

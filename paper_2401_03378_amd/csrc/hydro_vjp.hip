@@ -386,7 +386,7 @@ __device__ __forceinline__ void line_coords(int t, int e1, int e2, int &i, int &
     else { i = e1; j = e2; k = t; }
 }
 
-template <int NDIM, int RECON, int D>
+template <int NDIM, int RECON, int D, bool SHOCK>
 __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, int lane)
 {
     constexpr int R = (RECON == kWENO) ? 2 : 1;
@@ -474,7 +474,8 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
             for (int q = 0; q < NS; ++q)
 #pragma unroll
                 for (int v = 0; v < 5; ++v) s[q][v] = Wwin[q + 1][v];
-            const bool fb = recon_cell<NDIM, RECON>(s, qm, qp, A.eps);
+            // the forward's branches: positivity fallback and (SHOCK) the detector's flag
+            const bool fb = recon_cell<NDIM, RECON>(s, qm, qp, A.eps, SHOCK && shock_flag<D, R>(s, A.sthresh));
             double gqp_c1[5] = {0, 0, 0, 0, 0}, gqm_c[5] = {0, 0, 0, 0, 0};
             if (c >= f0) {
                 // cotangent of face c-1/2: gD_{c-1} - gD_c
@@ -541,15 +542,16 @@ __device__ __forceinline__ void vjp_line(const VjpArgs &A, const WorkItem &it, i
 }
 
 // One launch for every direction and segment: work item cost field =
-// direction | segment << 4.
-template <int NDIM, int RECON>
+// direction | segment << 4.  SHOCK: the shock detector's flags are among the
+// branches the reverse pass follows.
+template <int NDIM, int RECON, bool SHOCK>
 __global__ void __launch_bounds__(64) k_vjp_lines(VjpArgs A)
 {
     const WorkItem it = A.items[blockIdx.x];
     const int dir = it.cost & 15;
-    if (dir == 0) vjp_line<NDIM, RECON, 0>(A, it, threadIdx.x);
-    else if (dir == 1) vjp_line<NDIM, RECON, 1>(A, it, threadIdx.x);
-    else if constexpr (NDIM == 3) vjp_line<NDIM, RECON, 2>(A, it, threadIdx.x);
+    if (dir == 0) vjp_line<NDIM, RECON, 0, SHOCK>(A, it, threadIdx.x);
+    else if (dir == 1) vjp_line<NDIM, RECON, 1, SHOCK>(A, it, threadIdx.x);
+    else if constexpr (NDIM == 3) vjp_line<NDIM, RECON, 2, SHOCK>(A, it, threadIdx.x);
 }
 
 // ------------------------------------------------------------ cell kernel
@@ -659,9 +661,23 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
             }
             double gu[5];
             eos_vjp<NDIM>(u, gw, gu, A.g1);
+            // gravity source: T_{m_d} gains dt rho g_d and T_E gains dt (m . g)
+            const bool grv = (A.phys & kGravity) != 0;
+            double gsrc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (grv) {
+                const double dtv = *A.dt;
+                const double gTE = A.b * go[NV - 1];
+#pragma unroll
+                for (int d = 0; d < NDIM; ++d) {
+                    const double gTm = A.b * go[1 + d];
+                    gsrc[0] += dtv * (A.grav[d] * gTm);
+                    gsrc[1 + d] = dtv * (A.grav[d] * gTE);
+                }
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double gs = A.b * go[v] + gu[v];
+                double gs = A.b * go[v] + gu[v];
+                if (grv) gs = gs + gsrc[v];
                 if (A.last) {
                     A.gUn[v * nc + ci] = gn[v] + gs;
                 } else {
@@ -741,12 +757,23 @@ hipError_t launch_vjp_xpose(const VjpArgs &a, int ndim, int recon, hipStream_t s
 hipError_t launch_vjp_lines(const VjpArgs &a, int ndim, int recon, int nitems, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
+    const bool shock = (a.phys & kShock) != 0;
     if (ndim == 3) {
-        if (recon == kWENO) k_vjp_lines<3, kWENO><<<nitems, 64, 0, st>>>(a);
-        else k_vjp_lines<3, kPLM><<<nitems, 64, 0, st>>>(a);
+        if (recon == kWENO) {
+            if (shock) k_vjp_lines<3, kWENO, true><<<nitems, 64, 0, st>>>(a);
+            else k_vjp_lines<3, kWENO, false><<<nitems, 64, 0, st>>>(a);
+        } else {
+            if (shock) k_vjp_lines<3, kPLM, true><<<nitems, 64, 0, st>>>(a);
+            else k_vjp_lines<3, kPLM, false><<<nitems, 64, 0, st>>>(a);
+        }
     } else {
-        if (recon == kWENO) k_vjp_lines<2, kWENO><<<nitems, 64, 0, st>>>(a);
-        else k_vjp_lines<2, kPLM><<<nitems, 64, 0, st>>>(a);
+        if (recon == kWENO) {
+            if (shock) k_vjp_lines<2, kWENO, true><<<nitems, 64, 0, st>>>(a);
+            else k_vjp_lines<2, kWENO, false><<<nitems, 64, 0, st>>>(a);
+        } else {
+            if (shock) k_vjp_lines<2, kPLM, true><<<nitems, 64, 0, st>>>(a);
+            else k_vjp_lines<2, kPLM, false><<<nitems, 64, 0, st>>>(a);
+        }
     }
     return hipGetLastError();
 }

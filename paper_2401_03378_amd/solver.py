@@ -69,7 +69,8 @@ class Solver:
                 rc = self._L.hydro_create(C.byref(P), B, L, nb, self.ncell,
                                           C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
             else:
-                P.flags = _hip.FLAG_LEVEL_BY_LEVEL if level_by_level else 0
+                if level_by_level:
+                    P.flags |= _hip.FLAG_LEVEL_BY_LEVEL
                 rc = self._L.hydro_create_amr(C.byref(P), B, L, A, nb, self.ncell,
                                               C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         if rc != _hip.HYDRO_OK:

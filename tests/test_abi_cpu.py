@@ -61,6 +61,10 @@ def _mut(f):
     lambda p: setattr(p, "weno_eps", -1e-6),
     lambda p: setattr(p, "weno_eps", float("nan")),
     lambda p: setattr(p, "weno_eps", float("inf")),
+    lambda p: setattr(p, "grav", (float("nan"), 0.0, 0.0)),
+    lambda p: setattr(p, "grav", (0.0, 0.0, float("-inf"))),
+    lambda p: setattr(p, "shock_thresh", -0.5),
+    lambda p: setattr(p, "shock_thresh", float("nan")),
 ])
 def test_validate_rejects(f):
     assert _mut(f) == _hip.HYDRO_EINVAL
@@ -138,3 +142,20 @@ def test_cfl_dt_noalloc_rejects_bad_arguments_without_a_gpu():
         setattr(Q, field, bad)
         assert f(ctypes.byref(Q), fake, nb, p.ncell, fake, fake, None) == _hip.HYDRO_EINVAL
 
+
+def test_validate_physics_flags():
+    """Gravity and the shock detector: valid values pass, unknown flag bits
+    fail, and a mesh with levels refuses either."""
+    p = W.random_blocks(3, 6, 2, seed=0)
+    p.grav = (0.0, -9.8, 1.0)
+    p.shock_thresh = 0.0
+    assert _hip.validate(p) == _hip.HYDRO_OK
+    P, B, L, nb = _hip.tables(p)
+    assert P.flags == _hip.FLAG_GRAVITY | _hip.FLAG_SHOCK_DETECT
+    P.flags |= 8
+    assert _hip.lib().hydro_validate(ctypes.byref(P), B, L, nb, int(p.ncell)) == _hip.HYDRO_EINVAL
+    for attr, val in (("grav", (0.0, 1.0, 0.0)), ("shock_thresh", 0.5)):
+        q = W.amr_problem(2, n=8, ng=2, recon=0, rk=2)
+        assert _hip.validate(q) == _hip.HYDRO_OK
+        setattr(q, attr, val)
+        assert _hip.validate(q) == _hip.HYDRO_EINVAL
