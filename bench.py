@@ -134,9 +134,10 @@ def stage_kernel_time(S, U0, reps):
     Ua, B1, B2 = U0.clone(), U0.clone(), U0.clone()
     dt = S.cfl_dt(Ua)
     evs = []
+    chain = ((Ua, B1), (B1, B2), (B2, Ua)) if S.prob.rk == 3 else ((Ua, B1), (B1, Ua))
     with torch.cuda.stream(stream):
         for _ in range(reps):
-            for s, (Us, Uo) in enumerate(((Ua, B1), (B1, B2), (B2, Ua)), start=1):
+            for s, (Us, Uo) in enumerate(chain, start=1):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
@@ -305,6 +306,17 @@ def main():
                     help="only time the two-level AMR workload (prints its JSON object)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads, the adjoint/forward, per-block and copy comparisons")
+    ap.add_argument("--grav", type=float, nargs=3, default=None, metavar=("GX", "GY", "GZ"),
+                    help="add a uniform gravitational acceleration (grvAccel) to the workload")
+    ap.add_argument("--shock-thresh", type=float, default=None,
+                    help="turn on the shock detector (shockDet) with this relative pressure jump")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only time the checkpointed adjoint rollout of the workload (prints its JSON object)")
+    ap.add_argument("--adjoint-steps", type=int, default=None,
+                    help="steps of the adjoint rollout (default: 10 for turb3d, else the workload's)")
+    ap.add_argument("--adjoint-every", type=int, default=5, help="checkpoint interval of the adjoint rollout")
+    ap.add_argument("--tune", nargs="*", default=[], metavar="KEY=VALUE",
+                    help="override fields of the launch configuration after the autotuner (e.g. variant=2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the blocks are not sharded across GPUs, "
@@ -322,10 +334,16 @@ def main():
     build = {"turb3d": W.turb3d, "sedov3d": W.sedov3d, "batched": W.batched_uneven, "kh2d": W.kh2d,
              "sod2d": W.sod2d}[args.workload]
     prob = build()
+    if args.grav is not None:
+        prob.grav = tuple(args.grav)
+    if args.shock_thresh is not None:
+        prob.shock_thresh = args.shock_thresh
     zones = prob.interior_zones
     S = Solver(prob)
     if not args.no_autotune:
         autotune.tuned_or_search(S, prob, log=log)
+    if args.tune:
+        S.set_tuning(**{k: int(v) for k, v in (kv.split("=", 1) for kv in args.tune)})
     U0 = S.to_device(prob.U0)
     U = U0.clone()
     log(f"workload {prob.name}: {prob.nblocks} blocks, {zones} zones, tuning {S.tuning()}")
@@ -337,6 +355,14 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    nadj = args.adjoint_steps or (10 if prob.name == "turb3d" else prob.nsteps)
+    if args.adjoint_only:
+        res = {"workload": prob.name, "zones": zones, "tuning": S.tuning()}
+        res.update(adjoint_cost(S, U0, nadj, args.adjoint_every))
+        S.close()
+        print(json.dumps(res), flush=True)
+        return
 
     fused = not args.cfl_pass
     for _ in range(args.warmup):
@@ -386,7 +412,7 @@ def main():
                       "HLLC + SSP-RK3, CFL 0.5, gamma 1.4, k^-4 Gaussian velocity at rms Mach 0.5",
             "sedov3d": "sedov3d: 128^3 cells as 512 blocks of 16^3 + 3 guard layers, WENO5 + HLLC + SSP-RK3, "
                        "CFL 0.5, gamma 1.4, E=1 in r<3.5 cells",
-            "batched": "batched: 4096 periodic blocks (50% 8^3, 40% 16^3, 10% 32^3) + 2 guard layers, PLM-MC + "
+            "batched_uneven": "batched: 4096 periodic blocks (50% 8^3, 40% 16^3, 10% 32^3) + 2 guard layers, PLM-MC + "
                        "HLLC + SSP-RK2, CFL 0.8, gamma 5/3",
             "kh2d": "kh2d: 256^2 cells as 256 blocks of 16^2 + 2 guard layers, PLM-MC + HLLC + SSP-RK2",
             "sod2d": "sod2d: 64^2 cells as 16 blocks of 16^2 + 2 guard layers, PLM-MC + HLLC + SSP-RK2"}[prob.name]
@@ -403,7 +429,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "zones": zones, "rk_stages": prob.rk, "tuning": S.tuning(),
+        "config": {"workload": desc + ("" if prob.grav is None else f", gravity {tuple(prob.grav)}")
+                   + ("" if prob.shock_thresh is None else f", shock detector {prob.shock_thresh}"),
+                   "zones": zones, "rk_stages": prob.rk, "tuning": S.tuning(),
                    "dt": ("CFL maxima recorded by the previous step's final stage" if fused
                           else "separate CFL pass over U")},
         "repeats_ms_per_step": [round(r, 4) for r in reps],
@@ -413,10 +441,7 @@ def main():
         "balg_bytes_per_zone_stage": round(balg, 2),
     }
     if not args.no_extras:
-        if prob.name == "turb3d":
-            out.update(adjoint_cost(S, U0, 10, 5))
-        else:
-            out.update(adjoint_cost(S, U0, prob.nsteps, 5))
+        out.update(adjoint_cost(S, U0, nadj, args.adjoint_every))
         tpb = perblock_form(S, U0, 2)
         out["perblock_ms_per_step"] = round(tpb * 1e3, 3)
         out["speedup_vs_perblock"] = round(tpb * 1e3 / ms_per_step, 2)

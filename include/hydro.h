@@ -278,7 +278,7 @@ int hydro_step(hydro_ctx_t *ctx, double *U, double *dt_dev, int32_t compute_dt);
  * to rounding (summation order and reciprocal-based quotients in the
  * derivative arithmetic; relative error near 1e-15 per field), not bit for
  * bit.  The first call allocates the
- * ctx's adjoint scratch, (ndim x line segments + 4) x nvar x ncell_total
+ * ctx's adjoint scratch, (ndim x line segments + 3) x nvar x ncell_total
  * doubles, kept until hydro_destroy (HYDRO_ENOMEM if it cannot). */
 int hydro_step_vjp(hydro_ctx_t *ctx, const double *Un, const double *dt_dev,
                    const double *gUnext, double *gUn);

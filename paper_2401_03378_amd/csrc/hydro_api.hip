@@ -65,7 +65,7 @@ struct hydro_ctx {
     int nxitems = 0;
     int *d_inc_start = nullptr;
     int4 *d_inc = nullptr;
-    double *d_vjp = nullptr;     // gW per direction and segment | gA | gB | UsT | gOutT, each nvar x ncell
+    double *d_vjp = nullptr;     // gW per direction and segment | gS | UsT | gOutT, each nvar x ncell
     // telescoping: thick block copies, per-stage virtual (extended) blocks and work lists
     int tele_ready = 0;
     int ngt = 0;
@@ -768,7 +768,7 @@ int setup_vjp(hydro_ctx *c)
     if (!flat.empty())
         HIP_TRY(c, hipMemcpy(c->d_inc, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice));
     const size_t per = (size_t)c->nv * (size_t)std::max<int64_t>(1, c->ncell);
-    if (hipMalloc(&c->d_vjp, sizeof(double) * per * (size_t)(nd * c->nseg + 4)) != hipSuccess) {
+    if (hipMalloc(&c->d_vjp, sizeof(double) * per * (size_t)(nd * c->nseg + 3)) != hipSuccess) {
         c->d_vjp = nullptr;
         return fail(c, HYDRO_ENOMEM, "adjoint scratch");
     }
@@ -1298,10 +1298,15 @@ static int step_vjp(hydro_ctx_t *c, const double *Un, const double *const *stage
     }
     HIP_TRY(c, hipMemsetAsync(gUn, 0, sizeof(double) * per, st));
     const size_t narr = (size_t)nd * c->nseg;
-    double *gW = c->d_vjp, *gbuf[2] = {c->d_vjp + narr * per, c->d_vjp + (narr + 1) * per};
-    double *UsT = c->d_vjp + (narr + 2) * per, *gOutT = c->d_vjp + (narr + 3) * per;
+    // one stage-cotangent array: the last stage reads the caller's gUnext and
+    // writes gS; every earlier stage reads and writes gS in place (the cell
+    // kernel reads a cell's output cotangent before writing the same cell's
+    // input cotangent, and the transpose and line kernels, which read the
+    // output cotangents of other cells, have finished by then)
+    double *gW = c->d_vjp, *gS = c->d_vjp + narr * per;
+    double *UsT = c->d_vjp + (narr + 1) * per, *gOutT = c->d_vjp + (narr + 2) * per;
     const double *g = gUnext;
-    for (int s = S, q = 0; s >= 1; --s, q ^= 1) {
+    for (int s = S; s >= 1; --s) {
         VjpArgs v{};
         v.blocks = c->d_blocks;
         v.faces = c->d_faces;
@@ -1320,7 +1325,7 @@ static int step_vjp(hydro_ctx_t *c, const double *Un, const double *const *stage
         v.Us = Us_of[s];
         v.gOut = g;
         v.gW = gW;
-        v.gUs = gbuf[q];
+        v.gUs = gS;
         v.gUn = gUn;                 // s >= 2: += a gOut; s = 1: += gU_1
         v.last = (s == 1) ? 1 : 0;
         v.inc_start = c->d_inc_start;
@@ -1339,7 +1344,7 @@ static int step_vjp(hydro_ctx_t *c, const double *Un, const double *const *stage
         if (el != hipSuccess) return hip_fail(c, el, "adjoint line launch");
         hipError_t e = launch_vjp_cells(v, nd, c->prm.recon, c->ncitems, st);
         if (e != hipSuccess) return hip_fail(c, e, "adjoint cell launch");
-        g = gbuf[q];
+        g = gS;
     }
     return HYDRO_OK;
 }

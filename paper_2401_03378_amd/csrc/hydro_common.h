@@ -122,13 +122,16 @@ __device__ __forceinline__ bool eos(const double (&u)[5], double (&w)[5], double
 __device__ __forceinline__ void plm(double qa, double q0, double qb, double &qm, double &qp)
 {
     const double dm = q0 - qa, dp = qb - q0;
-    double s = 0.0;
-    if ((dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0)) {
-        const double a = 0.5 * (dm + dp);
-        const double aa = fabs(a), m2 = 2.0 * fabs(dm), p2 = 2.0 * fabs(dp);
-        const double lim = dmin(aa, dmin(m2, p2));
-        s = copysign(lim, a);
-    }
+    // the limited slope, evaluated for every lane and kept where the one-sided
+    // differences have the same strict sign (else 0): no divergent branch
+    const bool same = (dm > 0.0 && dp > 0.0) || (dm < 0.0 && dp < 0.0);
+    const double a = 0.5 * (dm + dp);
+    const double aa = fabs(a), m2 = 2.0 * fabs(dm), p2 = 2.0 * fabs(dp);
+    // the hardware minimum: where its result is kept, its operands are >= 0
+    // and never NaN (the differences passed strict sign tests), and there it
+    // equals the (a <= b) ? a : b rule of the method bit for bit
+    const double lim = fmin(aa, fmin(m2, p2));
+    const double s = same ? copysign(lim, a) : 0.0;
     qp = q0 + 0.5 * s;
     qm = q0 - 0.5 * s;
 }
@@ -296,8 +299,11 @@ __device__ __forceinline__ bool hllc(const double (&WL)[5], const double (&WR)[5
     if constexpr (ONE_SIDE) {
         const double rL = 1.0 / WL[0], rR = 1.0 / WR[0];
         const double cL = sqrt((K.gamma * WL[4]) * rL), cR = sqrt((K.gamma * WR[4]) * rR);
-        const double SL = dmin(uL - cL, uR - cR);
-        const double SR = dmax(uL + cL, uR + cR);
+        // hardware min/max: for physical states the speeds are finite and
+        // never -0 (c > 0), where they equal the (a <= b) ? a : b rule bit for
+        // bit; a non-physical state is reported whatever the flux
+        const double SL = fmin(uL - cL, uR - cR);
+        const double SR = fmax(uL + cL, uR + cR);
         const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
         const double Ss = ((WR[4] - WL[4]) + (mL * uL - mR * uR)) / (mL - mR);
         const bool subL = !(SL >= 0.0);
@@ -318,8 +324,8 @@ __device__ __forceinline__ bool hllc(const double (&WL)[5], const double (&WR)[5
         double UL[5], UR[5], FL[5], FR[5], rL, rR, cL, cR;
         state_flux_rc<NDIM, N>(WL, UL, FL, rL, cL, K);
         state_flux_rc<NDIM, N>(WR, UR, FR, rR, cR, K);
-        const double SL = dmin(uL - cL, uR - cR);
-        const double SR = dmax(uL + cL, uR + cR);
+        const double SL = fmin(uL - cL, uR - cR);   // as in the one-sided form
+        const double SR = fmax(uL + cL, uR + cR);
         const double mL = WL[0] * (SL - uL), mR = WR[0] * (SR - uR);
         const double Ss = ((WR[4] - WL[4]) + (mL * uL - mR * uR)) / (mL - mR);
         if (SL >= 0.0) {

@@ -640,7 +640,7 @@ __global__ void __launch_bounds__(TX *TY) k_vjp_cells(VjpArgs A)
             // guard positions (of this or other blocks) that copy this cell
             for (int e = inc0; e < inc1; ++e) {
                 const int4 q = A.inc[e];                 // x = block, y = dir, z = side, w = kind
-                const DevBlock X = A.blocks[q.x];
+                const DevBlock &X = A.blocks[q.x];    // read in place: a local copy with fields picked at run time would go to LDS
                 const int d = q.y;
                 const int pos = (d == 0) ? i : ((d == 1) ? j : k);
                 const int nb = (d == 0) ? B.nx : ((d == 1) ? B.ny : B.nz);
