@@ -313,8 +313,9 @@ int hydro_step_vjp_stages(hydro_ctx_t *ctx, const double *Un, const double *cons
  *   stream      hipStream_t (NULL: the default stream); asynchronous.
  * On valid blocks and physical states dt equals hydro_cfl_dt's for the same
  * problem bit for bit.  A block whose descriptor the kernel finds out of
- * range (extents < 1, 2D nz != 1, offset < 0 or its padded cells beyond
- * ncell_total; none of its cells is then read) or a non-physical cell
+ * range (extents outside 1..32767, ng outside 0..32767, 2D nz != 1,
+ * offset < 0 or its padded cells beyond ncell_total; none of its cells is
+ * then read) or a non-physical cell
  * (rho <= 0, p <= 0, NaN) makes dt NaN: with no context, that is the report.
  * Returns HYDRO_EINVAL for a null pointer, bad params, nblocks out of range
  * or ncell_total < 1 (text in hydro_last_error(NULL)), HYDRO_EHIP if the

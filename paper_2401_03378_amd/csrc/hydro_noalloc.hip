@@ -35,15 +35,16 @@ __global__ void __launch_bounds__(256) k_cfl_blocks(const hydro_block_t *__restr
     __shared__ double red[4];
     const int tid = threadIdx.x;
     const hydro_block_t B = blocks[blockIdx.x];
-    const int px = B.nx + 2 * B.ng, py = B.ny + 2 * B.ng;
-    const int gz = (NDIM == 3) ? B.ng : 0;
-    const int pz = B.nz + 2 * gz;
-    bool ok = B.nx >= 1 && B.ny >= 1 && B.nz >= 1 && B.ng >= 0 && B.offset >= 0 && B.offset < nc &&
+    // extents bounded as hydro_validate bounds them, so the padded sizes below
+    // cannot overflow
+    constexpr int32_t kMaxExtent = 32767;
+    bool ok = B.nx >= 1 && B.ny >= 1 && B.nz >= 1 && B.nx <= kMaxExtent && B.ny <= kMaxExtent &&
+              B.nz <= kMaxExtent && B.ng >= 0 && B.ng <= kMaxExtent && B.offset >= 0 && B.offset < nc &&
               (NDIM == 3 || B.nz == 1);
-    if (ok) {
-        const int64_t plane = (int64_t)px * py;
-        ok = (nc - B.offset) / plane >= pz;   // offset + px py pz <= nc, without overflow
-    }
+    const int64_t gz = (NDIM == 3) ? B.ng : 0;
+    const int64_t px = (int64_t)B.nx + 2 * (int64_t)B.ng, py = (int64_t)B.ny + 2 * (int64_t)B.ng;
+    const int64_t pz = (int64_t)B.nz + 2 * gz;
+    if (ok) ok = (nc - B.offset) / (px * py) >= pz;   // offset + px py pz <= nc, without overflow
     double m = 0.0;
     bool bad = !ok;
     if (ok) {
@@ -53,7 +54,7 @@ __global__ void __launch_bounds__(256) k_cfl_blocks(const hydro_block_t *__restr
             const int64_t r = q / B.nx;
             const int j = (int)(r % B.ny);
             const int k = (int)(r / B.ny);
-            const int64_t ci = B.offset + ((int64_t)(k + gz) * py + (j + B.ng)) * px + (i + B.ng);
+            const int64_t ci = B.offset + ((k + gz) * py + (j + B.ng)) * px + (i + B.ng);
             double u[5], wv[5];
             load_cons<NDIM>(U, nc, ci, u);
             bad |= eos<NDIM>(u, wv, g1);

@@ -346,7 +346,7 @@ def turb3d(N=256, n=16, ng=3, seed=0, nsteps=20, cfl=0.5, recon=WENO5, rk=3,
     vel = []
     for d in range(3):
         w = rs[d].standard_normal((N, N, N))
-        vel.append(np.fft.irfftn(np.fft.rfftn(w) * filt, s=(N, N, N)))
+        vel.append(np.fft.irfftn(np.fft.rfftn(w) * filt, s=(N, N, N), axes=(0, 1, 2)))
     rms = math.sqrt(float(np.mean(vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)))
     vel = [v * (mach / rms) for v in vel]
     rho = np.ones((N, N, N))

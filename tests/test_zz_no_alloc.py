@@ -66,6 +66,19 @@ def test_noalloc_reports_a_nonphysical_cell_and_a_bad_descriptor_as_nan():
     q.blocks["offset"][2] = q.ncell                          # padded cells beyond the state: not read
     U = torch.as_tensor(np.ascontiguousarray(q.U0), dtype=torch.float64).to(dev)
     assert math.isnan(float(_noalloc_dt(q, U)))
+    r = W.sod2d(N=32, n=16)
+    r.blocks = np.array(r.blocks, copy=True)
+    r.blocks["nx"][1] = 2 ** 31 - 1                          # an extent whose padded size would overflow 32 bits
+    assert math.isnan(float(_noalloc_dt(r, U)))
     # the valid problem right after still gets its own dt
+    U = torch.as_tensor(np.ascontiguousarray(p.U0), dtype=torch.float64).to(dev)
+    assert (_bits(_noalloc_dt(p, U)) == _bits(_ctx_dt(p, U))).all()
+
+
+def test_noalloc_dt_at_full_size():
+    """4096 blocks of 16^3 (the 256^3 turbulence workload): the same dt as
+    the context's, bit for bit."""
+    dev = torch.device("cuda:0")
+    p = W.turb3d()
     U = torch.as_tensor(np.ascontiguousarray(p.U0), dtype=torch.float64).to(dev)
     assert (_bits(_noalloc_dt(p, U)) == _bits(_ctx_dt(p, U))).all()
