@@ -154,3 +154,79 @@ def test_physics_step_vjp(k):
     S.close()
     assert_parity(p, got, ref, "physics step_vjp")
     assert np.all(got[:, ~W.interior_mask(p.blocks, p.ncell, p.ndim)] == 0.0)
+
+
+def test_turbulence_full_size_with_detector_and_gravity():
+    """The 256^3 turbulence workload (4096 blocks of 16^3) with the detector
+    and gravity in its tuned launch configuration: one step bit for bit, and
+    the step VJP at full size to 1e-12."""
+    from paper_2401_03378_amd import autotune
+    import json
+    import os
+    p = _with(W.turb3d(), (0.3, -0.5, 0.2), 0.3)
+    Uo, dto = _ora_run(p, 1)
+    tune = None
+    if os.path.exists(autotune.CACHE):
+        tune = json.load(open(autotune.CACHE)).get(autotune.signature(p), {}).get("tuning")
+    Ug, dtg = _gpu_run(p, 1, **(tune or {}))
+    assert np.array_equal(dtg, dto)
+    assert_parity(p, Ug, Uo, "turb256 physics", bitwise=True)
+    dt = float(dto[0])
+    rng = np.random.default_rng(77)
+    g = np.where(np.isfinite(p.U0), rng.standard_normal(p.U0.shape), 0.0)
+    ref = O.step_vjp(p, p.U0, dt, g)
+    S = _solver(p)
+    got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
+    S.status()
+    S.close()
+    assert_parity(p, got, ref, "turb256 physics step_vjp")
+
+
+def test_physics_central_differences():
+    """Central differences of two steps with gravity and the shock detector
+    on (smooth random data with a threshold that flags a share of the cells),
+    with the kink check of the plain-problem test: a direction whose
+    perturbation moves the adjoint by more than O(h) crossed a branch (a
+    detector flag, a limiter case, an HLLC region) and is left out; every
+    other direction must agree to 1e-6."""
+    p = _with(W.random_blocks(2, 16, 2, seed=9, amp=0.1, NB=(4, 4, 1)), (0.7, -1.3, 0.0), 0.02)
+    S = _solver(p)
+    m = np.isfinite(p.U0)
+    U0 = S.to_device(p.U0)
+    Ug = p.U0.copy()
+    O.fill_guards(p, Ug)
+    assert sum(int(O.shock_flags(p, Ug, d).sum()) for d in range(2)) > 20
+    dt = float(S.cfl_dt(U0).item())
+    rng = np.random.default_rng(11)
+    w = torch.nan_to_num(S.to_device(np.where(m, rng.standard_normal(p.U0.shape), 0.0)))
+
+    def grad_at(U):
+        U1 = U.clone()
+        S.step(U1, dt)
+        return S.step_vjp(U, S.step_vjp(U1, w, dt), dt)
+
+    g0 = grad_at(U0)
+    scale = float(g0.abs().max())
+    accepted, rejected = 0, []
+    for trial in range(40):
+        v = S.to_device(np.where(m, rng.standard_normal(p.U0.shape), 0.0))
+        h = 1e-7 * float(torch.nan_to_num(U0).abs().max()) / float(v.abs().max())
+        up, um = U0 + h * v, U0 - h * v
+        dev = max(float((grad_at(up) - g0).abs().max()), float((grad_at(um) - g0).abs().max())) / scale
+        if dev > 1e-5:
+            rejected.append(dev)
+            continue
+        for U in (up, um):
+            S.step(U, dt)
+            S.step(U, dt)
+        fd = float(torch.nansum(w * (up - um))) / (2 * h)
+        ad = float(torch.nansum(g0 * v))
+        assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (trial, fd, ad)
+        accepted += 1
+        if accepted >= 8:
+            break
+    S.status()
+    S.close()
+    print(f"central differences with gravity and the detector: {accepted} directions agree; "
+          f"{len(rejected)} crossed a branch")
+    assert accepted >= 8
