@@ -143,6 +143,8 @@ std::string check_problem(const hydro_params_t *p, const hydro_block_t *blocks, 
         if (B.nx > 32767 || B.ny > 32767 || B.nz > 32767) return "block " + std::to_string(b) + ": extent too large";
         if (B.ng < ngmin) return "block " + std::to_string(b) + ": ng below the stencil's need";
         if (p->ndim == 2 && B.nz != 1) return "block " + std::to_string(b) + ": 2D block with nz != 1";
+        if (p->ndim == 3 && (int64_t)(B.nx + 2 * (int64_t)B.ng) * (B.ny + 2 * (int64_t)B.ng) > INT32_MAX)
+            return "block " + std::to_string(b) + ": padded plane of 2^31 cells or more";
         const int64_t sz = padded_cells(B, p->ndim);
         if (B.offset < 0 || B.offset + sz > ncell) return "block " + std::to_string(b) + ": offset out of range";
         span[b] = {B.offset, B.offset + sz};

@@ -57,8 +57,11 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
     __shared__ double sW[5][LY][LX];
     __shared__ double sQx[5][TY][TX + 1];
     __shared__ double sQy[5][TY + 1][TX];
-    __shared__ double sFx[NV][TY][TX + 1];
-    __shared__ double sFy[NV][TY + 1][TX];
+    // the face fluxes take the place of the face states: each slot is read
+    // (its left state) and then written (its flux) by the one thread that
+    // solves that face, and the next write of a state follows a barrier
+    auto &sFx = sQx;
+    auto &sFy = sQy;
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -119,6 +122,32 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
             lj = off + H;
             return src_cell<1, GATHER>(B, F6, x0 + col, y0 + off, k);
         };
+        // The halo cells a thread loads, as the index in the item's first plane,
+        // the plane stride and the LDS slot: a halo cell's index is affine in
+        // the plane (its source block and transverse position do not change
+        // along z), so two evaluations per work item replace the per-plane
+        // gather arithmetic.  The stride is a source block's padded plane
+        // size, below 2^31 (checked on the host); 2D items have one plane.
+        int64_t hc0[NSLOT];
+        int32_t hst[NSLOT];
+        int hls[NSLOT];
+#pragma unroll
+        for (int q = 0; q < NSLOT; ++q) {
+            const int e = tid + q * NT;
+            hc0[q] = 0;
+            hst[q] = 0;
+            hls[q] = 0;
+            if (e < nhalo) {
+                int li, lj;
+                hc0[q] = halo_cell(e, z0, li, lj);
+                if constexpr (NDIM == 3) hst[q] = (int32_t)(halo_cell(e, z0 + 1, li, lj) - hc0[q]);
+                hls[q] = lj * LX + li;
+            }
+        }
+        auto halo_at = [&](int q, int kk) -> int64_t {
+            if constexpr (NDIM == 3) return hc0[q] + (int64_t)kk * hst[q];
+            return hc0[q];
+        };
         auto prefetch = [&](int k) {
             if (own) {
                 if constexpr (NDIM == 3)
@@ -132,10 +161,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
                 const int e = tid + q * NT;
-                if (e < nhalo) {
-                    int li, lj;
-                    load_cons<NDIM>(A.Us, nc, halo_cell(e, k, li, lj), ph[q]);
-                }
+                if (e < nhalo) load_cons<NDIM>(A.Us, nc, halo_at(q, k - z0), ph[q]);
             }
         };
         if constexpr (!PF) set_prio(3);
@@ -186,30 +212,35 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                     for (int v = 0; v < 5; ++v) chalo[q][v] = ph[q][v];
                 if (kk + 1 < nzc) prefetch(k + 1);
             }
+            // z face k+1/2 of the own column: the new cell k+H enters the z
+            // window, cell k+1 is reconstructed and the face solved
+            auto zface = [&]() {
+                double u[5];
+                if constexpr (PF) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) u[v] = cz[v];
+                } else {
+                    load_cons<NDIM>(A.Us, nc, src_cell<2, GATHER>(B, F6, i, j, k + H), u);
+                }
+                bad |= eos<NDIM>(u, zw[NW - 1], K.g1);
+                double qm[5], qp[5], Fhi[5];
+                recon_cell<NDIM, RECON>(zw, qm, qp, A.eps, shk && shock_flag<2, R>(zw, A.sthresh));   // cell k+1
+                bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Fhi, K);
+                if (k == B.nz - 1) reg_put(5, i, j, Fhi);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) { Dz[v] = Fhi[v] - Flo[v]; Flo[v] = Fhi[v]; }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) qpz[v] = qp[v];
+#pragma unroll
+                for (int c = 0; c < NW - 1; ++c)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) zw[c][v] = zw[c + 1][v];
+            };
             if (own) {
                 if constexpr (NDIM == 3) {
-                    double u[5];
-                    if constexpr (PF) {
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) u[v] = cz[v];
-                    } else {
-                        load_cons<NDIM>(A.Us, nc, src_cell<2, GATHER>(B, F6, i, j, k + H), u);
-                    }
-                    bad |= eos<NDIM>(u, zw[NW - 1], K.g1);
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = zw[R - 1][v];
-                    double qm[5], qp[5], Fhi[5];
-                    recon_cell<NDIM, RECON>(zw, qm, qp, A.eps, shk && shock_flag<2, R>(zw, A.sthresh));   // cell k+1
-                    bad |= hllc<NDIM, 2, RECON == kPLM>(qpz, qm, Fhi, K);
-                    if (k == B.nz - 1) reg_put(5, i, j, Fhi);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) { Dz[v] = Fhi[v] - Flo[v]; Flo[v] = Fhi[v]; }
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) qpz[v] = qp[v];
-#pragma unroll
-                    for (int c = 0; c < NW - 1; ++c)
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) zw[c][v] = zw[c + 1][v];
+                    for (int v = 0; v < 5; ++v) sW[v][ty + H][tx + H] = zw[R - 1][v];   // cell k
+                    zface();
                 } else {
                     double u[5], wv[5];
                     if constexpr (PF) {
@@ -224,42 +255,33 @@ __device__ __forceinline__ void stage_body(const StageArgs &A)
                 }
             }
             // x and y halo of plane k
-            if constexpr (PF) {
+            if constexpr (NDIM == 3 || PF) {
 #pragma unroll
                 for (int q = 0; q < NSLOT; ++q) {
-                    const int e = tid + q * NT;
-                    if (e < nhalo) {
-                        int li, lj;
-                        (void)halo_cell(e, k, li, lj);
-                        double wv[5];
-                        bad |= eos<NDIM>(chalo[q], wv, K.g1);
+                    if (tid + q * NT < nhalo) {
+                        double u[5], wv[5];
+                        if constexpr (PF) {
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) sW[v][lj][li] = wv[v];
+                            for (int v = 0; v < 5; ++v) u[v] = chalo[q][v];
+                        } else {
+                            load_cons<NDIM>(A.Us, nc, halo_at(q, kk), u);
+                        }
+                        bad |= eos<NDIM>(u, wv, K.g1);
+                        double *d = &sW[0][0][0] + hls[q];
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) d[v * LY * LX] = wv[v];
                     }
                 }
-            }
-            for (int e = PF ? nhalo : tid; e < nhalo; e += NT) {
-                int li, lj;
-                int64_t ci;
-                if (e < 2 * H * wy) {
-                    const int row = e / (2 * H), c = e % (2 * H);
-                    const int off = (c < H) ? c - H : wx + (c - H);   // -H..-1, wx..wx+H-1
-                    li = off + H;
-                    lj = row + H;
-                    ci = src_cell<0, GATHER>(B, F6, x0 + off, y0 + row, k);
-                } else {
-                    const int e2 = e - 2 * H * wy;
-                    const int c = e2 / wx, col = e2 % wx;
-                    const int off = (c < H) ? c - H : wy + (c - H);
-                    li = col + H;
-                    lj = off + H;
-                    ci = src_cell<1, GATHER>(B, F6, x0 + col, y0 + off, k);
-                }
-                double u[5], wv[5];
-                load_cons<NDIM>(A.Us, nc, ci, u);
-                bad |= eos<NDIM>(u, wv, K.g1);
+            } else {
+                // a 2D item is one plane: its halo is gathered once
+                for (int e = tid; e < nhalo; e += NT) {
+                    int li, lj;
+                    double u[5], wv[5];
+                    load_cons<NDIM>(A.Us, nc, halo_cell(e, k, li, lj), u);
+                    bad |= eos<NDIM>(u, wv, K.g1);
 #pragma unroll
-                for (int v = 0; v < 5; ++v) sW[v][lj][li] = wv[v];
+                    for (int v = 0; v < 5; ++v) sW[v][lj][li] = wv[v];
+                }
             }
             __syncthreads();
 

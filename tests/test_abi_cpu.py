@@ -81,6 +81,22 @@ def test_validate_mismatched_faces_and_weno_guards():
     assert _hip.validate(q) == _hip.HYDRO_EINVAL
 
 
+def test_validate_plane_size_bound():
+    """A 3D block's padded xy plane must hold fewer than 2^31 cells (the
+    stage kernels step a halo cell's index from plane to plane by that
+    size in 32 bits): one periodic block of 30000 x 30000 x 9000 cells
+    passes with ng = 3 and is refused with ng = 9000 (48000^2 > 2^31)."""
+    def one(ng):
+        blocks, ncell = W.make_table([(30000, 30000, 9000)], ng, 3)
+        links = np.zeros(1, dtype=W.LINK_DTYPE)
+        links["nbr"] = [0, 0, 0, 0, 0, 0]
+        p = W.random_blocks(3, 6, 2, seed=0)
+        p.blocks, p.links, p.ncell = blocks, links, ncell
+        return _hip.validate(p)
+    assert one(3) == _hip.HYDRO_OK
+    assert one(9000) == _hip.HYDRO_EINVAL
+
+
 def test_validate_amr_meshes_and_broken_tables():
     """Host-only check of a mesh with refinement levels: generated meshes
     pass; a link that disagrees with the level table, a level gap, a wrong
