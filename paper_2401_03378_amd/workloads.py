@@ -384,6 +384,35 @@ def random_blocks(ndim, sizes, ng, seed, recon=PLM_MC, rk=2, gamma=1.4, cfl=0.8,
                    (NB[0], NB[1], NB[2], n))
 
 
+def rectilinear(ndim, widths, ng, seed, recon=PLM_MC, rk=2, gamma=1.4, cfl=0.8, bc="periodic", amp=0.3):
+    """Random smooth-free state on a block grid whose columns, rows (and
+    layers) have their own widths (test fixtures): widths = (wx, wy[, wz]),
+    block (i, j, k) has wx[i] x wy[j] x wz[k] cells, so neighbours across a
+    face share that face's size but not their extent along its normal (nor
+    their padded plane size).  Block index (k*NBy + j)*NBx + i."""
+    wx, wy = list(widths[0]), list(widths[1])
+    wz = list(widths[2]) if ndim == 3 else [1]
+    NB = (len(wx), len(wy), len(wz))
+    sizes = [(wx[i], wy[j], wz[k]) for k in range(NB[2]) for j in range(NB[1]) for i in range(NB[0])]
+    blocks, ncell = make_table(sizes, ng, ndim)
+    _, links, _ = uniform_grid(NB, 1, ng, ndim, bc)       # the same block graph
+    (r,) = _streams(seed, 1)
+    shp = (sum(wz), sum(wy), sum(wx))
+    rho = np.exp(amp * r.standard_normal(shp))
+    p = np.exp(amp * r.standard_normal(shp))
+    c = np.sqrt(gamma * p / rho)
+    vel = [amp * c * r.standard_normal(shp) for _ in range(ndim)]
+    G = conserved(rho, vel, p, gamma)
+    U = empty_state(ndim + 2, ncell)
+    ox, oy, oz = np.cumsum([0] + wx), np.cumsum([0] + wy), np.cumsum([0] + wz)
+    for b in range(len(sizes)):
+        i, j, k = b % NB[0], (b // NB[0]) % NB[1], b // (NB[0] * NB[1])
+        interior(U, blocks, b, ndim)[...] = G[:, oz[k]:oz[k + 1], oy[j]:oy[j + 1], ox[i]:ox[i + 1]]
+    dx = 1.0 / sum(wx)
+    return Problem("rectilinear", ndim, recon, rk, gamma, cfl, dx, dx, dx if ndim == 3 else 1.0,
+                   blocks, links, ncell, 1, U, seed)
+
+
 def free_fall(ndim, n=8, ng=2, recon=PLM_MC, rk=2, NB=None, grav=(0.3, -2.0, 0.5), rho=1.3,
               vel=(0.2, -0.1, 0.3), p=0.7, gamma=1.4, cfl=0.8):
     """A uniform gas in a periodic box under a uniform gravitational

@@ -100,6 +100,37 @@ def test_parity_small_all_tiles(ndim, recon, rk, n, ng, bc, NB):
             assert np.array_equal(first[:, m], Ug[:, m])
 
 
+UNEVEN = [
+    # ndim, recon, rk, bc, widths
+    (3, 1, 3, "periodic", ((8, 12, 16), (10, 6), (9, 7))),
+    (3, 0, 2, "outflow", ((6, 9, 13), (7, 5), (11, 4))),
+    (3, 1, 3, "outflow", ((3, 17, 5), (20, 4), (6, 3))),
+    (2, 1, 3, "periodic", ((8, 12, 16), (10, 6))),
+    (2, 0, 2, "outflow", ((5, 19, 2), (9, 33))),
+]
+
+
+@pytest.mark.parametrize("ndim,recon,rk,bc,widths", UNEVEN)
+def test_uneven_neighbours_all_launch_forms(ndim, recon, rk, bc, widths):
+    """Blocks whose neighbours differ in their extent along the shared
+    face's normal, so a halo cell's source block has another padded plane
+    (its index steps through the planes by that block's plane size): every
+    tile, z-chunking, schedule, grid and launch form gives the oracle's
+    states and dts bit for bit."""
+    from paper_2401_03378_amd import _hip
+    ng = 3 if recon == 1 else 2
+    p = W.rectilinear(ndim, widths, ng, seed=17, recon=recon, rk=rk, bc=bc)
+    Uo, dto = _ora_run(p, 3)
+    tunes = [dict(tile=t, zchunk=z, variant=v) for t in (0, 1, 2) for z in ((0, 5) if ndim == 3 else (0,))
+             for v in (0, 1)]
+    tunes += [dict(tile=2, grid=16, xcd=1), dict(tile=1, grid=64, xcd=2, zchunk=3 if ndim == 3 else 0),
+              dict(mode=_hip.MODE_PERBLOCK), dict(mode=_hip.MODE_MATERIALISED, tile=0)]
+    for tune in tunes:
+        Ug, dtg = _gpu_run(p, 3, **tune)
+        assert np.array_equal(dtg, dto), tune
+        assert_parity(p, Ug, Uo, f"uneven {tune}", bitwise=True)
+
+
 def test_sod_full_config():
     p = W.config(0)
     Uo, dto = _ora_run(p, p.nsteps)

@@ -431,6 +431,93 @@ def test_block_decomposition_invariance(ndim):
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+def _gather_rectilinear(U, p, widths):
+    """Global interior array of a rectilinear block grid (the layout of
+    W.rectilinear)."""
+    ws = [list(w) for w in widths] + ([[1]] if p.ndim == 2 else [])
+    o = [np.cumsum([0] + w) for w in ws]
+    G = np.empty((U.shape[0], o[2][-1], o[1][-1], o[0][-1]))
+    NB = [len(w) for w in ws]
+    for b in range(p.nblocks):
+        i, j, k = b % NB[0], (b // NB[0]) % NB[1], b // (NB[0] * NB[1])
+        G[:, o[2][k]:o[2][k + 1], o[1][j]:o[1][j + 1], o[0][i]:o[0][i + 1]] = W.interior(U, p.blocks, b, p.ndim)
+    return G
+
+
+UNEVEN_CASES = [(2, 0, 2, "periodic"), (2, 1, 3, "outflow"), (3, 0, 2, "outflow"), (3, 1, 3, "periodic")]
+
+
+def _uneven_decomposition_check(step, ndim, recon, rk, bc):
+    ng = 3 if recon == 1 else 2
+    even = ((12, 12, 12), (12, 12), (12, 12))[:ndim]
+    uneven = ((8, 12, 16), (10, 14), (9, 15))[:ndim]
+    outs = []
+    for widths in (even, uneven):
+        p = W.rectilinear(ndim, widths, ng, seed=13, recon=recon, rk=rk, bc=bc)
+        U = p.U0.copy()
+        dts = [step(p, U) for _ in range(2)]
+        outs.append((dts, _gather_rectilinear(U, p, widths)))
+    assert not np.array_equal(outs[1][1], _gather_rectilinear(p.U0, p, uneven))
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("ndim,recon,rk,bc", UNEVEN_CASES)
+def test_uneven_block_decomposition_invariance(ndim, recon, rk, bc):
+    """The same global field cut into blocks of equal size and into blocks
+    whose neighbours differ in their extent along the shared face's normal
+    (so a guard layer is gathered from a block of another padded shape)
+    gives the same two steps bit for bit: a cell's update reads only cell
+    values, and where they sit in memory must not matter."""
+    _uneven_decomposition_check(O.step, ndim, recon, rk, bc)
+
+
+# the guard fill's read of its source cell, and a plausible slip in it: the
+# source block's offset with the filled block's own padded shape (the same
+# thing on a mesh of equal blocks)
+_GUARD_SRC = "                            int64_t si = FN(cell)(&P->blocks[sb], nd, s[0], s[1], s[2]);"
+_GUARD_SLIP = ("                            int64_t si = P->blocks[sb].offset - B->offset + "
+               "FN(cell)(B, nd, s[0], s[1], s[2]);")
+
+
+def test_uneven_decomposition_rejects_a_guard_stride_slip(tmp_path):
+    import ctypes as C
+    import shutil
+    import subprocess
+    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+    src = open(os.path.join(d, "forward_body.inc")).read()
+    assert src.count(_GUARD_SRC) == 1, "the guard fill's source changed: update the slip"
+    for f in ("oracle.c", "oracle_cs.c", "oracle_amr.c", "oracle.h"):
+        shutil.copy(os.path.join(d, f), tmp_path / f)
+    (tmp_path / "forward_body.inc").write_text(src.replace(_GUARD_SRC, _GUARD_SLIP))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+                    "-std=gnu11", "-o", str(lib), "oracle.c", "oracle_cs.c", "oracle_amr.c", "-lm"],
+                   check=True, cwd=tmp_path, capture_output=True)
+    L = C.CDLL(str(lib))
+    f = L.ora_step
+    f.restype = C.c_int
+    f.argtypes = [C.POINTER(O._Problem), C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int]
+
+    def step(p, U):
+        P = O.Problem(p)
+        dt = np.zeros(1)
+        rc = f(P.ptr, U.ctypes.data_as(C.POINTER(C.c_double)), dt.ctypes.data_as(C.POINTER(C.c_double)), 1)
+        assert rc == O.ORA_OK, rc
+        return float(dt[0])
+
+    # the slip is invisible on equal blocks ...
+    p = W.rectilinear(3, ((12, 12), (12, 12), (12, 12)), 3, seed=13, recon=1, rk=3)
+    U, V = p.U0.copy(), p.U0.copy()
+    assert step(p, U) == O.step(p, V)
+    m = W.interior_mask(p.blocks, p.ncell, 3)
+    assert np.array_equal(U[:, m], V[:, m])
+    # ... and fails the uneven decomposition
+    for case in UNEVEN_CASES:
+        with pytest.raises(AssertionError):
+            _uneven_decomposition_check(step, *case)
+
+
 def test_nan_padding_untouched_by_stencils():
     """Every input carries NaN in all padding; a read of an edge or corner, or
     of a guard before it is filled, would show up as NaN in the interior."""
