@@ -50,10 +50,10 @@ __device__ __forceinline__ void wave_vjp(const double (&w)[5], double r, double 
                                          double (&gW)[5], const Consts &K)
 {
     const double p = w[4];
-    const double gx = gc * rcp_nr(2.0 * c);
-    gW[4] += gx * K.gamma * r;
-    const double grt = gr + gx * K.gamma * p;
-    gW[0] += -r * r * grt;
+    const double gxg = (gc * rcp_nr(2.0 * c)) * K.gamma;
+    gW[4] = fma(gxg, r, gW[4]);
+    const double grt = fma(gxg, p, gr);
+    gW[0] = fma(-r * r, grt, gW[0]);
 }
 
 // Reverse of U and F of a face state (state_flux without c and r).
@@ -70,30 +70,28 @@ __device__ __forceinline__ void cons_flux_vjp(const double (&w)[5], const double
         u2 = w[1] * w[1] + w[2] * w[2];
     const double E = p * K.ig1 + 0.5 * (rho * u2);
     const double fr = rho * un;
-    double grho = 0.0, gp = 0.0, gE = 0.0, gu[3] = {0.0, 0.0, 0.0};
+    // the derivative arithmetic in fused multiply-adds
+    double gu[3] = {0.0, 0.0, 0.0};
     double gfr = gF[0];
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
-        gfr += gF[1 + d] * w[1 + d];
-        gu[d] += gF[1 + d] * fr;
+        gfr = fma(gF[1 + d], w[1 + d], gfr);
+        gu[d] = gF[1 + d] * fr;
     }
-    gp += gF[1 + N];
-    gE += gF[NV - 1] * un;
-    gp += gF[NV - 1] * un;
-    gu[N] += gF[NV - 1] * (E + p);
-    grho += gfr * un;
-    gu[N] += gfr * rho;
-    grho += gU[0];
+    double gp = fma(gF[NV - 1], un, gF[1 + N]);
+    double gE = fma(gF[NV - 1], un, gU[NV - 1]);
+    gu[N] = fma(gF[NV - 1], E + p, fma(gfr, rho, gu[N]));
+    double grho = fma(gfr, un, gU[0]);
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
-        grho += gU[1 + d] * w[1 + d];
-        gu[d] += gU[1 + d] * rho;
+        grho = fma(gU[1 + d], w[1 + d], grho);
+        gu[d] = fma(gU[1 + d], rho, gu[d]);
     }
-    gE += gU[NV - 1];
-    gp += gE * K.ig1;
-    grho += gE * 0.5 * u2;
+    gp = fma(gE, K.ig1, gp);
+    grho = fma(gE * 0.5, u2, grho);
+    const double gEr = gE * rho;
 #pragma unroll
-    for (int d = 0; d < NDIM; ++d) gu[d] += gE * rho * w[1 + d];
+    for (int d = 0; d < NDIM; ++d) gu[d] = fma(gEr, w[1 + d], gu[d]);
     gW[0] += grho;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) gW[1 + d] += gu[d];
@@ -162,32 +160,31 @@ __device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&W
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) Us[1 + d] = (d == N) ? chi * Ss : chi * W[1 + d];
     Us[NV - 1] = chi * Bq;
+    // the derivative arithmetic in fused multiply-adds
     double gSK = 0.0, gUs[5], gUK[5];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        gSK += gF[v] * (Us[v] - UK[v]);
+        gSK = fma(gF[v], Us[v] - UK[v], gSK);
         gUs[v] = SK * gF[v];
-        gUK[v] = -(SK * gF[v]);
+        gUK[v] = -gUs[v];
     }
     double gWK[5] = {0, 0, 0, 0, 0};
-    double gchi = gUs[0] + gUs[1 + N] * Ss + gUs[NV - 1] * Bq;
+    double gchi = fma(gUs[NV - 1], Bq, fma(gUs[1 + N], Ss, gUs[0]));
 #pragma unroll
     for (int d = 0; d < NDIM; ++d)
         if (d != N) {
-            gchi += gUs[1 + d] * W[1 + d];
-            gWK[1 + d] += gUs[1 + d] * chi;
+            gchi = fma(gUs[1 + d], W[1 + d], gchi);
+            gWK[1 + d] = gUs[1 + d] * chi;
         }
-    double gSs = gUs[1 + N] * chi;
     const double gB = gUs[NV - 1] * chi;
-    gUK[NV - 1] += gB * rK;
+    gUK[NV - 1] = fma(gB, rK, gUK[NV - 1]);
     const double grK = gB * UK[NV - 1];
-    gSs += gB * (Ss + q) + gB * (Ss - uK);
-    gWK[1 + N] -= gB * (Ss + q);
+    double gSs = fma(gB, (Ss + q) + (Ss - uK), gUs[1 + N] * chi);
+    gWK[1 + N] = -(gB * (Ss + q));
     const double gq = gB * (Ss - uK);
-    gWK[4] += gq * imK;
-    double gmK = -gq * q * imK;
-    gmK += gchi * iden;
-    const double gden = -gchi * chi * iden;
+    gWK[4] = gq * imK;
+    const double gmK = fma(-gq * q, imK, gchi * iden);
+    const double gden = -(gchi * chi) * iden;
     gSK += gden;
     gSs -= gden;
     cons_flux_vjp<NDIM, N>(W, gUK, gF, gWK, K);          // F_K + terms through U_K
@@ -202,18 +199,18 @@ __device__ __forceinline__ void hllc_vjp(const double (&WL)[5], const double (&W
         for (int v = 0; v < 5; ++v) gWL[v] += gWK[v];
     }
     const double iDen = rcp_nr(Den);
-    const double gN = gSs * iDen, gD = -gSs * Ss * iDen;
+    const double gN = gSs * iDen, gD = -(gSs * Ss) * iDen;
     gWR[4] += gN;
     gWL[4] -= gN;
-    gmL += gN * uL + gD;
-    gmR += -gN * uR - gD;
-    double guL = gN * mL, guR = -gN * mR;
-    gWL[0] += gmL * (SL - uL);
-    gSL += gmL * WL[0];
-    guL -= gmL * WL[0];
-    gWR[0] += gmR * (SR - uR);
-    gSR += gmR * WR[0];
-    guR -= gmR * WR[0];
+    gmL += fma(gN, uL, gD);
+    gmR -= fma(gN, uR, gD);
+    double guL = gN * mL, guR = -(gN * mR);
+    gWL[0] = fma(gmL, SL - uL, gWL[0]);
+    gSL = fma(gmL, WL[0], gSL);
+    guL = fma(-gmL, WL[0], guL);
+    gWR[0] = fma(gmR, SR - uR, gWR[0]);
+    gSR = fma(gmR, WR[0], gSR);
+    guR = fma(-gmR, WR[0], guR);
     if (slR) { guR += gSL; gcR -= gSL; } else { guL += gSL; gcL -= gSL; }
     if (srR) { guR += gSR; gcR += gSR; } else { guL += gSR; gcL += gSR; }
     gWL[1 + N] += guL;
@@ -242,11 +239,20 @@ __device__ __forceinline__ void plm_vjp(double qa, double q0, double qb, double 
 }
 
 // Reverse of WENO5-JS on (a,b,c,d,e): adds to g[0..4].
+//
+// Forward: beta_k = 13/12 t_k^2 + 1/4 w_k^2, sq_k = eps + beta_k,
+// s_k = sq_k^2, o_k = the product of the two other s_j, and per face the
+// value sum(d_k o_k p_k) / sum(d_k o_k) of the candidates p_k (the left face
+// mirrors the stencil and takes the weights in the order o_2, o_1, o_0).
+// The face values are recomputed here for their derivatives only (one
+// reciprocal per face), and the derivative arithmetic, which is held to a
+// tolerance rather than to the forward's bits, uses fused multiply-adds.
+// The recomputed indicators and candidates are written unlike the forward
+// reconstruction's expressions: the compiler would otherwise carry the
+// forward's values of a cell over to its reverse one position later, which
+// does not fit in the registers of two waves per SIMD.
 __device__ __forceinline__ void weno5_vjp(const double *q, double eps, double gqm, double gqp, double *g)
 {
-    // Forward: s_k = (eps + beta_k)^2, o_k = product of the two other s_j,
-    // face value = sum(d_k o_k p_k) / sum(d_k o_k).  One reciprocal per face
-    // (the face value is recomputed here for its derivatives only).
     const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0;
     const double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
     double t[3], w[3], sq[3], s[3];
@@ -262,8 +268,8 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double eps, double gq
         s[k] = sq[k] * sq[k];
     }
     const double o[3] = {s[1] * s[2], s[0] * s[2], s[0] * s[1]};
-    double go0 = 0.0, go1 = 0.0, go2 = 0.0;
-    {   // right face
+    double go0, go1, go2;
+    {   // right face; u_k: the cotangents of the candidates p_k over 6
         const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * k6;
         const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;
         const double p2 = ((2.0 * c + 5.0 * d) - e) * k6;
@@ -271,15 +277,16 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double eps, double gq
         const double iS = rcp_nr((a0 + a1) + a2);
         const double gS = gqp * iS;
         const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
-        const double gp0 = gS * a0, gp1 = gS * a1, gp2 = gS * a2;
-        go0 += 0.1 * gS * (p0 - qv);
-        go1 += 0.6 * gS * (p1 - qv);
-        go2 += 0.3 * gS * (p2 - qv);
-        g[0] += k6 * (2.0 * gp0);
-        g[1] += k6 * (-7.0 * gp0 - gp1);
-        g[2] += k6 * (11.0 * gp0 + 5.0 * gp1 + 2.0 * gp2);
-        g[3] += k6 * (2.0 * gp1 + 5.0 * gp2);
-        g[4] += k6 * (-gp2);
+        go0 = (0.1 * gS) * (p0 - qv);
+        go1 = (0.6 * gS) * (p1 - qv);
+        go2 = (0.3 * gS) * (p2 - qv);
+        const double gSk = gS * k6;
+        const double u0 = gSk * a0, u1 = gSk * a1, u2 = gSk * a2;
+        g[0] = fma(2.0, u0, g[0]);
+        g[1] = g[1] - fma(7.0, u0, u1);
+        g[2] = fma(11.0, u0, fma(5.0, u1, fma(2.0, u2, g[2])));
+        g[3] = fma(2.0, u1, fma(5.0, u2, g[3]));
+        g[4] = g[4] - u2;
     }
     {   // left face: mirrored candidates, weights (0.1 o2, 0.6 o1, 0.3 o0)
         const double p0 = ((2.0 * e - 7.0 * d) + 11.0 * c) * k6;
@@ -289,30 +296,33 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double eps, double gq
         const double iS = rcp_nr((a0 + a1) + a2);
         const double gS = gqm * iS;
         const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
-        const double gp0 = gS * a0, gp1 = gS * a1, gp2 = gS * a2;
-        go2 += 0.1 * gS * (p0 - qv);
-        go1 += 0.6 * gS * (p1 - qv);
-        go0 += 0.3 * gS * (p2 - qv);
-        g[4] += k6 * (2.0 * gp0);
-        g[3] += k6 * (-7.0 * gp0 - gp1);
-        g[2] += k6 * (11.0 * gp0 + 5.0 * gp1 + 2.0 * gp2);
-        g[1] += k6 * (2.0 * gp1 + 5.0 * gp2);
-        g[0] += k6 * (-gp2);
+        go2 = fma(0.1 * gS, p0 - qv, go2);
+        go1 = fma(0.6 * gS, p1 - qv, go1);
+        go0 = fma(0.3 * gS, p2 - qv, go0);
+        const double gSk = gS * k6;
+        const double u0 = gSk * a0, u1 = gSk * a1, u2 = gSk * a2;
+        g[4] = fma(2.0, u0, g[4]);
+        g[3] = g[3] - fma(7.0, u0, u1);
+        g[2] = fma(11.0, u0, fma(5.0, u1, fma(2.0, u2, g[2])));
+        g[1] = fma(2.0, u1, fma(5.0, u2, g[1]));
+        g[0] = g[0] - u2;
     }
-    // o_0 = s_1 s_2, o_1 = s_0 s_2, o_2 = s_0 s_1
-    const double gs[3] = {go1 * s[2] + go2 * s[1], go0 * s[2] + go2 * s[0], go0 * s[1] + go1 * s[0]};
-    double gt[3], gw[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double gbe = 2.0 * sq[k] * gs[k];
-        gt[k] = 2.0 * k13 * t[k] * gbe;
-        gw[k] = 0.5 * w[k] * gbe;
-    }
-    g[0] += gt[0] + gw[0];
-    g[1] += -2.0 * gt[0] - 4.0 * gw[0] + gt[1] + gw[1];
-    g[2] += gt[0] + 3.0 * gw[0] - 2.0 * gt[1] + gt[2] + 3.0 * gw[2];
-    g[3] += gt[1] - gw[1] - 2.0 * gt[2] - 4.0 * gw[2];
-    g[4] += gt[2] + gw[2];
+    // o -> s -> beta: beta_k receives 2 sq_k gs_k (gs_k: the cotangent of
+    // s_k); with G_k = sq_k gs_k, t_k receives 4 k13 t_k G_k and w_k w_k G_k
+    const double G0 = sq[0] * fma(go1, s[2], go2 * s[1]);
+    const double G1 = sq[1] * fma(go0, s[2], go2 * s[0]);
+    const double G2 = sq[2] * fma(go0, s[1], go1 * s[0]);
+    const double k4 = 4.0 * k13;
+    const double gt0 = (k4 * t[0]) * G0, gw0 = w[0] * G0;
+    const double gt1 = (k4 * t[1]) * G1, gw1 = w[1] * G1;
+    const double gt2 = (k4 * t[2]) * G2, gw2 = w[2] * G2;
+    // the indicators' stencils: t_0 = a - 2b + c, w_0 = a - 4b + 3c,
+    // t_1 = b - 2c + d, w_1 = b - d, t_2 = c - 2d + e, w_2 = 3c - 4d + e
+    g[0] = g[0] + (gt0 + gw0);
+    g[1] = fma(-2.0, gt0, fma(-4.0, gw0, g[1] + (gt1 + gw1)));
+    g[2] = fma(-2.0, gt1, fma(3.0, gw0 + gw2, g[2] + (gt0 + gt2)));
+    g[3] = fma(-2.0, gt2, fma(-4.0, gw2, g[3] + (gt1 - gw1)));
+    g[4] = g[4] + (gt2 + gw2);
 }
 
 // Reverse of one cell's reconstruction along a line: s[c][v] stencil
