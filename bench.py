@@ -291,7 +291,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed steps before the timed ones (the GPU clocks settle over the first few)")
     ap.add_argument("--repeats", type=int, default=5, help="timed loops of --steps steps (the first is the line's value)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work (0 = skip)")
     ap.add_argument("--kernel-steps", type=int, default=5, help="steps timed per stage launch with events")
