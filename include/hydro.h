@@ -171,9 +171,10 @@ typedef struct hydro_ctx hydro_ctx_t;
 
 /* Host-only check of a problem description (no GPU use).  Returns HYDRO_OK
  * or HYDRO_EINVAL: null pointer, ndim/recon/rk out of range, gamma <= 1,
- * cfl or dx <= 0, weno_eps not finite and > 0, extents < 1, ng below the stencil's need, 2D block with
- * nz != 1, offsets out of range or overlapping, link index out of range,
- * neighbour faces that do not match. */
+ * cfl or dx <= 0, weno_eps not finite and > 0, extents outside 1..32767, ng
+ * below the stencil's need, 2D block with nz != 1, 3D block whose padded xy
+ * plane (nx+2ng)(ny+2ng) holds 2^31 cells or more, offsets out of range or
+ * overlapping, link index out of range, neighbour faces that do not match. */
 int hydro_validate(const hydro_params_t *params, const hydro_block_t *blocks,
                    const hydro_link_t *links, int32_t nblocks, int64_t ncell_total);
 
