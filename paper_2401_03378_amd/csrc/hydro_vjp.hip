@@ -245,38 +245,41 @@ __device__ __forceinline__ void plm_vjp(double qa, double q0, double qb, double 
 // value sum(d_k o_k p_k) / sum(d_k o_k) of the candidates p_k (the left face
 // mirrors the stencil and takes the weights in the order o_2, o_1, o_0).
 // The face values are recomputed here for their derivatives only (one
-// reciprocal per face), and all of this arithmetic, which is held to a
+// reciprocal per face), and the derivative arithmetic, which is held to a
 // tolerance rather than to the forward's bits, uses fused multiply-adds.
-// The recomputed indicators and candidates are grouped unlike the forward
-// reconstruction's expressions: written alike, the compiler would carry the
-// forward's values of a cell over to its reverse one position later, which
-// does not fit in the registers of two waves per SIMD.
+// The recomputed indicators and candidates stay in separate multiplies and
+// adds, unlike the forward reconstruction's fused expressions: written alike,
+// the compiler would carry the forward's values of a cell over to its
+// reverse one position later, which does not fit in the registers of two
+// waves per SIMD; and fused in another grouping, their rounding departs
+// from the reference reverse's where a candidate nearly equals the face
+// value (p_k - q cancels), which costs two to three digits of agreement.
 __device__ __forceinline__ void weno5_vjp(const double *q, double eps, double gqm, double gqp, double *g)
 {
     const double k13 = 13.0 / 12.0, k6 = 1.0 / 6.0;
     const double a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
     double t[3], w[3], sq[3], s[3];
-    t[0] = fma(-2.0, b, a + c);
-    w[0] = fma(-4.0, b, fma(3.0, c, a));
-    t[1] = fma(-2.0, c, b + d);
+    t[0] = (a - 2.0 * b) + c;
+    w[0] = (a - 4.0 * b) + 3.0 * c;
+    t[1] = (b - 2.0 * c) + d;
     w[1] = b - d;
-    t[2] = fma(-2.0, d, c + e);
-    w[2] = fma(-4.0, d, fma(3.0, c, e));
+    t[2] = (c - 2.0 * d) + e;
+    w[2] = (3.0 * c - 4.0 * d) + e;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        sq[k] = fma(k13 * t[k], t[k], fma(0.25 * w[k], w[k], eps));
+        sq[k] = eps + (k13 * (t[k] * t[k]) + 0.25 * (w[k] * w[k]));
         s[k] = sq[k] * sq[k];
     }
     const double o[3] = {s[1] * s[2], s[0] * s[2], s[0] * s[1]};
     double go0, go1, go2;
     {   // right face; u_k: the cotangents of the candidates p_k over 6
-        const double p0 = k6 * fma(11.0, c, fma(-7.0, b, 2.0 * a));
-        const double p1 = k6 * fma(2.0, d, fma(5.0, c, -b));
-        const double p2 = k6 * fma(5.0, d, fma(2.0, c, -e));
+        const double p0 = ((2.0 * a - 7.0 * b) + 11.0 * c) * k6;
+        const double p1 = ((-b + 5.0 * c) + 2.0 * d) * k6;
+        const double p2 = ((2.0 * c + 5.0 * d) - e) * k6;
         const double a0 = 0.1 * o[0], a1 = 0.6 * o[1], a2 = 0.3 * o[2];
         const double iS = rcp_nr((a0 + a1) + a2);
         const double gS = gqp * iS;
-        const double qv = fma(a2, p2, fma(a1, p1, a0 * p0)) * iS;
+        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
         go0 = (0.1 * gS) * (p0 - qv);
         go1 = (0.6 * gS) * (p1 - qv);
         go2 = (0.3 * gS) * (p2 - qv);
@@ -289,13 +292,13 @@ __device__ __forceinline__ void weno5_vjp(const double *q, double eps, double gq
         g[4] = g[4] - u2;
     }
     {   // left face: mirrored candidates, weights (0.1 o2, 0.6 o1, 0.3 o0)
-        const double p0 = k6 * fma(11.0, c, fma(-7.0, d, 2.0 * e));
-        const double p1 = k6 * fma(2.0, b, fma(5.0, c, -d));
-        const double p2 = k6 * fma(5.0, b, fma(2.0, c, -a));
+        const double p0 = ((2.0 * e - 7.0 * d) + 11.0 * c) * k6;
+        const double p1 = ((-d + 5.0 * c) + 2.0 * b) * k6;
+        const double p2 = ((2.0 * c + 5.0 * b) - a) * k6;
         const double a0 = 0.1 * o[2], a1 = 0.6 * o[1], a2 = 0.3 * o[0];
         const double iS = rcp_nr((a0 + a1) + a2);
         const double gS = gqm * iS;
-        const double qv = fma(a2, p2, fma(a1, p1, a0 * p0)) * iS;
+        const double qv = ((a0 * p0 + a1 * p1) + a2 * p2) * iS;
         go2 = fma(0.1 * gS, p0 - qv, go2);
         go1 = fma(0.6 * gS, p1 - qv, go1);
         go0 = fma(0.3 * gS, p2 - qv, go0);
