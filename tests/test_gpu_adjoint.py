@@ -132,7 +132,10 @@ def test_turbulence_step_vjp_full_size():
     ref = O.step_vjp(p, p.U0, dt, g)
     S = _solver(p)
     got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
-    assert_parity(p, got, ref, "turb vjp 256^3")
+    errs = assert_parity(p, got, ref, "turb vjp 256^3")
+    # the observed agreement is ~4e-16; a change of the reverse arithmetic that
+    # keeps the tolerance but loses digits against the oracle fails here
+    assert max(e for e, _ in errs) <= 1e-14, errs
     S.close()
 
 
@@ -145,7 +148,8 @@ def test_sedov_step_vjp_full_size_and_rollout():
     ref = O.step_vjp(p, p.U0, dt, g)
     S = _solver(p, **(_bench_tuning(p) or {}))
     got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
-    assert_parity(p, got, ref, "sedov vjp 128^3")
+    errs = assert_parity(p, got, ref, "sedov vjp 128^3")
+    assert max(e for e, _ in errs) <= 1e-14, errs      # observed ~3e-15
     ost = OracleStepper(p)
     _, tape_o = rollout(ost, p.U0, 4, 2)
     g_o = rollout_vjp(ost, tape_o, g)
