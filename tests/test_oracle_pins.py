@@ -358,6 +358,15 @@ def test_cfl_dt_closed_form():
     p.dx = p.dy = p.dz = 1.0 / 64
     dt = O.cfl_dt(p, U)
     assert dt == 0.8 / (4.0 * 64 + 5.0 * 64 + 3.5 * 64)
+    # unequal cell widths: each direction's speed over its own width
+    p.dx, p.dy, p.dz = 1.0 / 64, 1.0 / 32, 1.0 / 128
+    assert O.cfl_dt(p, U) == 0.8 / (4.0 * 64 + 5.0 * 32 + 3.5 * 128)
+    # the fastest cell decides: one cell with u = (0, 0, 7) and the same c
+    i = int(np.flatnonzero(m)[17])
+    V = U.copy()
+    V[1, i], V[2, i], V[3, i] = 0.0, 0.0, rho * 7.0
+    V[4, i] = pr / 0.5 + 0.5 * rho * 49.0
+    assert O.cfl_dt(p, V) == 0.8 / (3.0 * 64 + 3.0 * 32 + 10.0 * 128)
 
 
 # ------------------------------------------------------ invariants (T5-T10)
