@@ -58,6 +58,8 @@ CASES = [
     ("atmosphere", lambda: W.atmosphere2d(N=64, n=16), (0.0, -1.0, 0.0), None, 20),
     ("free_fall_3d", lambda: W.free_fall(3, n=8, ng=3, recon=1, rk=3), G3, 0.5, 5),
     ("batched_uneven", lambda: W.batched_uneven(nblocks=40, seed=27), G3, 0.3, 3),
+    ("uneven_neighbours", lambda: W.rectilinear(3, ((8, 12, 6), (10, 5), (9, 7)), 3, seed=28, recon=1, rk=3,
+                                                bc="outflow"), G3, 0.2, 3),
 ]
 
 
