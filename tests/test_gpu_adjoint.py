@@ -86,6 +86,33 @@ def test_step_vjp_batched_uneven_blocks():
     S.close()
 
 
+UNEVEN = [
+    (3, 1, 3, "periodic", ((8, 12, 16), (10, 6), (9, 7))),
+    (3, 0, 2, "outflow", ((6, 9, 13), (7, 5), (11, 4))),
+    (3, 1, 3, "outflow", ((3, 17, 5), (20, 4), (6, 3))),
+    (2, 1, 3, "periodic", ((8, 12, 16), (10, 6))),
+    (2, 0, 2, "outflow", ((5, 19, 2), (9, 33))),
+]
+
+
+@pytest.mark.parametrize("ndim,recon,rk,bc,widths", UNEVEN)
+def test_step_vjp_uneven_neighbours(ndim, recon, rk, bc, widths):
+    """Blocks whose neighbours differ in their extent along the shared
+    face's normal: the guard cotangents are summed back into cells of blocks
+    of another padded shape (and the x lines' transposed copies span them)."""
+    ng = 3 if recon == 1 else 2
+    p = W.rectilinear(ndim, widths, ng, seed=19, recon=recon, rk=rk, bc=bc)
+    dt = O.cfl_dt(p, p.U0)
+    g = _rand_cot(p, 23)
+    ref = O.step_vjp(p, p.U0, dt, g)
+    S = _solver(p)
+    got = S.step_vjp(S.to_device(p.U0), S.to_device(g), dt).cpu().numpy()
+    S.status()
+    S.close()
+    assert_parity(p, got, ref, "step_vjp uneven neighbours")
+    assert np.all(got[:, ~W.interior_mask(p.blocks, p.ncell, ndim)] == 0.0)
+
+
 def test_kh_rollout_gradient_full_config():
     """50 steps of the 256^2 Kelvin-Helmholtz problem, loss
     sum (rho_T - rho_target)^2 with the target from perturbation seed+1,
