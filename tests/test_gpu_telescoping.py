@@ -38,6 +38,30 @@ def test_telescoping_parity(ndim, n, ng, recon, rk, bc, NB):
         assert_parity(p, Ug, Uo, f"telescoping tile {tile}", bitwise=True)
 
 
+@pytest.mark.parametrize("ndim,recon,rk,bc,widths", [
+    (3, 1, 3, "periodic", ((9, 12, 16), (10, 14), (9, 11))),
+    (3, 0, 2, "outflow", ((4, 9, 6), (7, 5), (11, 4))),
+    (2, 1, 3, "outflow", ((9, 20, 12), (10, 16))),
+])
+def test_telescoping_uneven_neighbours(ndim, recon, rk, bc, widths):
+    """Thick copies gathered from neighbours of other padded shapes: the
+    oracle's telescoping step bit for bit in every tile, and on the periodic
+    mesh the per-stage fill's result."""
+    ng = 3 if recon == 1 else 2
+    p = W.rectilinear(ndim, widths, ng, seed=29, recon=recon, rk=rk, bc=bc)
+    Uo = p.U0.copy()
+    dto = [O.step_telescoping(p, Uo) for _ in range(2)]
+    for tile in (0, 1, 2):
+        Ug, dtg = _run(p, 2, mode=2, tile=tile)
+        assert list(dtg) == dto
+        assert_parity(p, Ug, Uo, f"telescoping uneven tile {tile}", bitwise=True)
+    if bc == "periodic":
+        m = W.interior_mask(p.blocks, p.ncell, ndim)
+        Ua, da = _run(p, 2)
+        assert list(da) == dto
+        assert np.array_equal(Ua[:, m], Uo[:, m])
+
+
 def test_telescoping_equals_per_stage_fill_on_periodic_configs():
     for p, n in ((W.batched_uneven(nblocks=64, seed=2), 3), (W.kh2d(N=64, n=16), 4),
                  (W.turb3d(N=32, n=16, seed=1), 2)):
