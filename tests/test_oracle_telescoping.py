@@ -26,6 +26,20 @@ def test_telescoping_equals_per_stage_fill_on_periodic_domains(ndim, n, ng, reco
     assert np.array_equal(U1[:, m], U2[:, m])
 
 
+@pytest.mark.parametrize("ndim,recon,rk,widths", [
+    (3, 1, 3, ((9, 12, 16), (10, 14), (9, 11))), (3, 0, 2, ((4, 9, 6), (7, 5), (11, 4))),
+    (2, 1, 2, ((9, 20, 12), (10, 16)))])
+def test_telescoping_equals_per_stage_fill_with_uneven_neighbours(ndim, recon, rk, widths):
+    """Thick copies gathered from neighbours of other padded shapes (a block
+    grid whose columns, rows and layers have their own widths)."""
+    p = W.rectilinear(ndim, widths, 3 if recon == 1 else 2, seed=31, recon=recon, rk=rk, bc="periodic")
+    m = W.interior_mask(p.blocks, p.ncell, ndim)
+    U1, U2 = p.U0.copy(), p.U0.copy()
+    for _ in range(2):
+        assert O.step(p, U1) == O.step_telescoping(p, U2)
+    assert np.array_equal(U1[:, m], U2[:, m])
+
+
 def test_telescoping_batched_independent_blocks():
     p = W.batched_uneven(nblocks=24, seed=3)
     m = W.interior_mask(p.blocks, p.ncell, 3)
