@@ -380,12 +380,12 @@ def test_nonphysical_state_is_reported():
 
 
 @pytest.mark.parametrize("case", ["sedov", "turb", "kh", "batched", "outflow_weno"])
-@pytest.mark.parametrize("use_graph", [1, 0])
-def test_dt_from_previous_step_is_the_same_step(case, use_graph):
+@pytest.mark.parametrize("use_graph,variant", [(1, 0), (0, 0), (1, 1)])
+def test_dt_from_previous_step_is_the_same_step(case, use_graph, variant):
     """dt from the maxima the previous step's final stage recorded
     (HYDRO_DT_FROM_PREVIOUS): the same dts and states, bit for bit, as reading
-    U for every dt; after a stage written into U by hydro_rk_stage the
-    recorded maxima are not used."""
+    U for every dt, in the plain and the prefetching schedule; after a stage
+    written into U by hydro_rk_stage the recorded maxima are not used."""
     p = {"sedov": lambda: W.sedov3d(N=32, n=16),
          "turb": lambda: W.turb3d(N=32, n=16, seed=4),
          "kh": lambda: W.kh2d(N=64, seed=1),
@@ -394,7 +394,7 @@ def test_dt_from_previous_step_is_the_same_step(case, use_graph):
     m = W.interior_mask(p.blocks, p.ncell, p.ndim)
     out = {}
     for fused in (False, True):
-        S = _solver(p, use_graph=use_graph)
+        S = _solver(p, use_graph=use_graph, variant=variant)
         U = S.to_device(p.U0)
         dts = S.run(U, 5, dt_from_previous=fused).cpu().numpy()
         # a stage of the caller's own into U, then more steps
